@@ -1,0 +1,257 @@
+/*
+ * ttcconv.h -- C ABI of the MI355X (gfx950) library for direct n-D convolution,
+ * image pyramids, first-difference derivative cubes and multi-scale
+ * time-to-contact (TTC) / focus-of-expansion (FOE) estimation.
+ *
+ * Method: "Accelerated Convolutions for Efficient Multi-Scale Time to Contact
+ * Computation in Julia" (Amini, Horn, Edelman).  Each entry point names the
+ * passage of the paper that defines what it computes.
+ *
+ * Conventions shared by every entry point
+ *  - Every buffer is owned by the caller.  Data pointers inside tc_tensor and
+ *    the workspace are DEVICE pointers unless stated otherwise; descriptor
+ *    structs themselves (tc_tensor, tc_seq) are read on the host during the
+ *    call and may be freed when it returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    launch is asynchronous on that stream; no entry point synchronises except
+ *    tc_ttc_solve_batched and tc_ttc_plan_destroy, which say so.
+ *  - No entry point allocates or frees device memory.
+ *  - A negative return value means the arguments were rejected and nothing
+ *    was launched.  No C++ exception crosses this interface.
+ *  - Strides are in elements and row-major (the last dimension is the
+ *    fastest).  A stride of 0 on a dimension of extent > 1 is rejected.
+ */
+#ifndef TTCCONV_H
+#define TTCCONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes.  Positive values are per-result statuses (tc_ttc_level.status). */
+enum {
+  TC_OK = 0,
+  TC_SINGULAR = 1,   /* the 3x3 normal matrix is rank deficient (e.g. a linear-ramp video) */
+  TC_NEED_PREV = 2,  /* a stream has no previous frame yet (serving) */
+  TC_NONFINITE = 3,  /* a sum is NaN or infinite (non-finite input) */
+  TC_EINVAL = -1,    /* bad argument (NULL pointer, bad mode, too many levels, ...) */
+  TC_ESHAPE = -2,    /* inconsistent shapes or strides */
+  TC_EDTYPE = -3,    /* unsupported dtype combination */
+  TC_EOVERFLOW = -4, /* an exact integer result could exceed int32 */
+  TC_ENOMEM = -5,    /* workspace too small */
+  TC_EDEVICE = -6    /* HIP error or a device other than gfx950 */
+};
+
+/* Element types. */
+enum { TC_U8 = 0, TC_F16 = 1, TC_F32 = 2, TC_I32 = 3, TC_F64 = 4 };
+
+/* Convolution output modes. */
+enum { TC_FULL = 0, TC_SAME = 1, TC_VALID = 2 };
+
+#define TC_MAX_DIMS 8
+#define TC_MAX_LEVELS 4
+#define TC_NUM_SUMS 10
+
+/* A strided n-D array.  `data` is a device pointer (ignored by the pure
+ * shape queries). */
+typedef struct {
+  void* data;
+  int32_t dtype;
+  int32_t ndim;
+  int64_t shape[TC_MAX_DIMS];
+  int64_t stride[TC_MAX_DIMS];
+} tc_tensor;
+
+/* Human-readable name of a return code or status.  Never NULL. */
+const char* tc_status_str(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int tc_version(void);
+
+/* Checks that HIP device `device` is a gfx950 and returns its number of
+ * compute units in *n_cu (may be NULL).  TC_EDEVICE otherwise. */
+int tc_device_check(int device, int* n_cu);
+
+/* ------------------------------------------------------------------------
+ * Direct n-D convolution
+ *
+ * Discrete Derivatives section, the spatial convolution equation; the paper
+ * writes the sum as a correlation over the image extent, and it is read here
+ * as true convolution over the kernel extent (the routine the paper's
+ * Benchmarking subsection compares with), for arrays of any rank
+ * (Accelerating Convolutions: n-dimensional convolution):
+ *
+ *     y[n] = sum_m x[m] * k[n - m],  zero outside the extents of x and k.
+ *
+ * Modes: TC_FULL (extent N+K-1), TC_SAME (extent N, starting at (K-1)/2 of
+ * the full result), TC_VALID (extent |N-K|+1, starting at min(N,K)-1; needs
+ * N >= K in every dimension or K >= N in every dimension).  The kernel may be
+ * larger than x (full mode is commutative).
+ *
+ * dtypes (x, k -> y): F32,F32->F32; F16,F32->F32; U8,I32->I32 (exact; rejected
+ * with TC_EOVERFLOW unless 255 * sum|k| <= 2^31-1).  x and k have the same
+ * rank 1..8.  x and y may be strided; k must be contiguous and at most
+ * 2^20 elements, and is read from DEVICE memory.  y must not overlap x or k.
+ * Float results are accumulated in FP32 in kernel-row-major tap order.
+ * ------------------------------------------------------------------------ */
+int tc_conv_out_shape(const tc_tensor* x, const tc_tensor* k, int32_t mode, int64_t* out_shape);
+int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Image pyramid
+ *
+ * Time to Contact, Results: down-sampling by a block-averaging filter,
+ * repeated for several consecutive levels.  Read as the 2x2 block mean with
+ * no further low-pass filter; odd extents are floored:
+ *
+ *     P_{l+1}[i][j] = (P_l[2i][2j] + P_l[2i][2j+1] + P_l[2i+1][2j] + P_l[2i+1][2j+1]) / 4
+ *
+ * `frame` is a 2-D U8, F16 or F32 image (strided).  `out` points to an array
+ * of (levels - 1) 2-D F32 tensors (host array of descriptors, device data),
+ * out[l-1] receiving level l with extent floor(H/2^l) x floor(W/2^l).
+ * levels is 1..16; level levels-1 must be at least 1x1.  Exact for U8 frames.
+ * ------------------------------------------------------------------------ */
+int tc_pyramid_shape(int64_t H, int64_t W, int32_t level, int64_t* Hl, int64_t* Wl);
+int tc_image_pyramid(const tc_tensor* frame, int32_t levels, const tc_tensor* out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * First-difference derivative cube of one frame pair
+ *
+ * Discrete Derivatives section: the one-pixel forward difference (mask
+ * [-1, 1]) and its 2x2 form (1/2)[[-1, 1], [-1, 1]] for E_x (transpose for
+ * E_y), extended over the two frames of a pair:
+ *
+ *   E_x(i,j) = 1/4 sum_{a,c} [P_c(i+a,j+1) - P_c(i+a,j)]
+ *   E_y(i,j) = 1/4 sum_{b,c} [P_c(i+1,j+b) - P_c(i,j+b)]
+ *   E_t(i,j) = 1/4 sum_{a,b} [P_1(i+a,j+b) - P_0(i+a,j+b)]
+ *
+ * for 0 <= i <= H-2, 0 <= j <= W-2 (x = column, y = row).  prev and next are
+ * 2-D U8/F16/F32 images of the same shape and dtype.  ex, ey, et are
+ * (H-1) x (W-1): F32 outputs receive E (FP32, exact for U8 and rendered-F16
+ * data); I32 outputs (U8 input only) receive the exact numerators 4*E.
+ * ------------------------------------------------------------------------ */
+int tc_horn_derivs(const tc_tensor* prev, const tc_tensor* next, const tc_tensor* ex, const tc_tensor* ey,
+                   const tc_tensor* et, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Time to contact and focus of expansion
+ *
+ * Time to Contact, Formulation: with the radial gradient G = x E_x + y E_y,
+ * least squares of A E_x + B E_y + C G + E_t over every derivative cube gives
+ * the 3x3 normal equations
+ *
+ *   [S(ExEx) S(ExEy) S(GEx)] [A]     [S(ExEt)]
+ *   [S(ExEy) S(EyEy) S(GEy)] [B] = - [S(EyEt)]
+ *   [S(GEx)  S(GEy)  S(GG) ] [C]     [S(GEt) ]
+ *
+ * and then x0 = -A/C, y0 = -B/C, TTC = 1/C.  Results subsection: the same is
+ * done on each pyramid level, and the multi-scale estimate descends while the
+ * TTC estimate keeps decreasing.
+ *
+ * Readings: x, y are cube centres in base-image pixels from the base-image
+ * centre (x right, y down): a cube of level l between pixels (i,j) and
+ * (i+1,j+1) sits at x = 2^l (j+1) - W/2, y = 2^l (i+1) - H/2.  Spatial
+ * derivatives are per base pixel, so A, B, x0, y0 are in base pixels and C,
+ * TTC per frame at every level.  C > 0 for an approaching camera.  The 3x3
+ * system is solved in FP64 by Gaussian elimination with partial pivoting on
+ * the equilibrated matrix D M D (D = diag(M_ii^-1/2)); it is TC_SINGULAR when
+ * a diagonal entry is not positive or an equilibrated pivot is below 1e-6.
+ * Multi-scale: an estimate that is singular, non-finite or not positive counts
+ * as +infinity; descend from level 0 while the next level's estimate is
+ * smaller; stop at the first non-decrease.
+ *
+ * Precision: frames are U8 or F16; derivatives are formed in FP32 (exact for
+ * U8 and rendered-F16 frames at levels 0..3), products are FP32, each wave
+ * sums a block of cubes in FP32 and the blocks are combined with TwoSum
+ * (hi, lo) compensation; only the 3x3 solve is FP64.
+ * ------------------------------------------------------------------------ */
+
+/* The ten sums, in this order, in base-pixel units:
+ *   S(ExEx), S(ExEy), S(EyEy), S(GEx), S(GEy), S(GG), S(ExEt), S(EyEt), S(GEt), S(EtEt) */
+typedef struct {
+  double sums[TC_NUM_SUMS];
+  double A, B, C;
+  double ttc, x0, y0;
+  double resid;   /* sum of (A Ex + B Ey + C G + Et)^2 at the solution */
+  int64_t n;      /* number of cubes summed */
+  int32_t level;  /* pyramid level (0 = base) */
+  int32_t status; /* TC_OK, TC_SINGULAR or TC_NONFINITE; A..resid are NaN unless TC_OK */
+} tc_ttc_level;
+
+/* The multi-scale choice for one frame pair. */
+typedef struct {
+  double ttc, x0, y0;
+  double A, B, C;
+  int32_t level;  /* selected level */
+  int32_t status; /* status of the selected level */
+} tc_ttc_pick;
+
+/* A video stream of n_frames frames of H x W pixels.  Frame k starts at
+ * frame0 + k * frame_stride elements and row i of it at + i * row_stride.
+ * Pairs (k, k+1), k = 0 .. n_frames-2, are processed; each frame is read from
+ * memory once per pass.  A single pair of unrelated frames is a stream with
+ * n_frames = 2 and frame_stride = next - prev (in elements, may be negative). */
+typedef struct {
+  const void* frame0;
+  int64_t frame_stride;
+  int64_t row_stride;
+  int32_t H, W;
+  int32_t n_frames;
+  int32_t levels;
+} tc_seq;
+
+typedef struct tc_ttc_plan tc_ttc_plan;
+
+/* Validates a batch of streams (all of dtype U8 or F16, all with the same
+ * number of levels 1..TC_MAX_LEVELS, every level at least 2x2, H and W at most
+ * 2^20, row_stride >= W, frame0 aligned to the element size) and builds its
+ * work tables in pinned host memory.  Streams whose frames and rows start on
+ * 8-pixel boundaries are read with vector loads, others element by element.
+ * Host-only; *plan must be released with tc_ttc_plan_destroy.
+ * Output layout: stream-major, then pair, then level: stream s, pair p,
+ * level l is levels_out[pair_base(s) * L + p * L + l] and picks_out[pair_base(s) + p],
+ * pair_base(s) = sum over earlier streams of (n_frames - 1). */
+int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan);
+/* Workspace bytes the plan needs, the total number of pairs and the number
+ * of tc_ttc_level records (pairs * levels). */
+int tc_ttc_plan_info(const tc_ttc_plan* plan, size_t* ws_bytes, int64_t* n_pairs, int64_t* n_level_records);
+/* Asynchronously copies the plan's work tables into the workspace on
+ * `stream`; the plan must stay alive until the stream has passed the copy. */
+int tc_ttc_plan_upload(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, void* stream);
+/* Launches the fused pass (pyramid + derivative cube + products + block
+ * sums, persistent, each frame read once) and the finishing pass
+ * (compensated block reduction, FP64 solve, multi-scale choice).  Launches
+ * only: may be captured in a HIP graph.  Reads the frames through the
+ * pointers given at plan creation. */
+int tc_ttc_plan_run(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, tc_ttc_level* levels_out,
+                    tc_ttc_pick* picks_out, void* stream);
+/* The two launches of tc_ttc_plan_run separately: phase 1 is the fused pass
+ * (writes the per-wave partial sums into the workspace), phase 2 the finishing
+ * pass (reads them, writes levels_out and picks_out; may be NULL in phase 1).
+ * Phase 3 runs both.  For timing or overlapping the phases on a stream. */
+#define TC_PHASE_FUSED 1
+#define TC_PHASE_FINISH 2
+int tc_ttc_plan_run_phase(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, tc_ttc_level* levels_out,
+                          tc_ttc_pick* picks_out, int32_t phase, void* stream);
+/* Frees the plan (synchronises the device first). */
+void tc_ttc_plan_destroy(tc_ttc_plan* plan);
+
+/* Create + upload + run + stream synchronise + destroy, for one-off calls. */
+int tc_ttc_solve_batched(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, void* ws, size_t ws_bytes,
+                         tc_ttc_level* levels_out, tc_ttc_pick* picks_out, void* stream);
+
+/* Workspace bytes for tc_ttc_solve on an H x W pair with `levels` levels. */
+int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_t* ws_bytes);
+/* One frame pair (2-D U8 or F16 tensors of equal shape): levels_out[levels]
+ * and pick_out[1] in device memory.  Launches only (no host copy). */
+int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_t levels, void* ws, size_t ws_bytes,
+                 tc_ttc_level* levels_out, tc_ttc_pick* pick_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTCCONV_H */

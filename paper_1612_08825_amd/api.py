@@ -1,0 +1,242 @@
+"""Python binding of the C ABI: the same entry points, taking torch tensors.
+
+PyTorch supplies device memory and the current stream; every computation runs
+in the HIP kernels of libttcconv.so.  Functions raise when the library is not
+built or a tensor is not on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_DT = {torch.uint8: L.TC_U8, torch.float16: L.TC_F16, torch.float32: L.TC_F32, torch.int32: L.TC_I32,
+       torch.float64: L.TC_F64}
+
+
+def _lib():
+    return L.load()
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _desc(t: torch.Tensor) -> L.TcTensor:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if t.dtype not in _DT:
+        raise ValueError(f"unsupported dtype {t.dtype}")
+    d = L.TcTensor()
+    d.data = t.data_ptr() if t.numel() > 0 else None
+    d.dtype = _DT[t.dtype]
+    d.ndim = t.dim()
+    for i, (n, s) in enumerate(zip(t.shape, t.stride())):
+        d.shape[i] = n
+        d.stride[i] = s
+    return d
+
+
+def _shape_desc(shape, dtype_code: int) -> L.TcTensor:
+    d = L.TcTensor()
+    d.data = None
+    d.dtype = dtype_code
+    d.ndim = len(shape)
+    for i, n in enumerate(shape):
+        d.shape[i] = int(n)
+        d.stride[i] = 1
+    return d
+
+
+def version() -> int:
+    return _lib().tc_version()
+
+
+def device_check(device: int = 0) -> int:
+    """Number of compute units of a gfx950 device (raises on any other device)."""
+    n = C.c_int(0)
+    L.check("tc_device_check", _lib().tc_device_check(device, C.byref(n)))
+    return n.value
+
+
+# ----------------------------------------------------------------------------- convolution
+def conv_out_shape(xshape, kshape, mode: str = "full", xdtype=torch.float32, kdtype=torch.float32):
+    lib = _lib()
+    out = (C.c_int64 * L.TC_MAX_DIMS)()
+    L.check("tc_conv_out_shape", lib.tc_conv_out_shape(C.byref(_shape_desc(xshape, _DT[xdtype])),
+                                                       C.byref(_shape_desc(kshape, _DT[kdtype])),
+                                                       L.MODES[mode], out))
+    return tuple(out[i] for i in range(len(xshape)))
+
+
+def conv_nd(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[torch.Tensor] = None, stream=None):
+    """y = x (*) k, true n-D convolution (f32*f32->f32, f16*f32->f32, u8*i32->i32)."""
+    lib = _lib()
+    shape = conv_out_shape(tuple(x.shape), tuple(k.shape), mode, x.dtype, k.dtype)
+    ydt = torch.int32 if x.dtype == torch.uint8 else torch.float32
+    if out is None:
+        out = torch.empty(shape, dtype=ydt, device=x.device)
+    L.check("tc_conv_nd", lib.tc_conv_nd(C.byref(_desc(x)), C.byref(_desc(k)), L.MODES[mode], C.byref(_desc(out)),
+                                         _stream(stream)))
+    return out
+
+
+# ----------------------------------------------------------------------------- pyramid / derivatives
+def image_pyramid(frame: torch.Tensor, levels: int, stream=None) -> List[torch.Tensor]:
+    """[level 1, ..., level levels-1] as float32 tensors (level 0 is the frame itself)."""
+    lib = _lib()
+    H, W = frame.shape
+    outs = [torch.empty((H >> l, W >> l), dtype=torch.float32, device=frame.device) for l in range(1, levels)]
+    arr = (L.TcTensor * max(1, len(outs)))(*[_desc(o) for o in outs]) if outs else None
+    L.check("tc_image_pyramid", lib.tc_image_pyramid(C.byref(_desc(frame)), levels, arr, _stream(stream)))
+    return outs
+
+
+def horn_derivs(prev: torch.Tensor, nxt: torch.Tensor, exact_int: bool = False, stream=None):
+    """(E_x, E_y, E_t) of the first-difference cube; exact_int returns the int32 numerators 4E (u8 only)."""
+    lib = _lib()
+    H, W = prev.shape
+    dt = torch.int32 if exact_int else torch.float32
+    outs = [torch.empty((H - 1, W - 1), dtype=dt, device=prev.device) for _ in range(3)]
+    L.check("tc_horn_derivs", lib.tc_horn_derivs(C.byref(_desc(prev)), C.byref(_desc(nxt)), C.byref(_desc(outs[0])),
+                                                 C.byref(_desc(outs[1])), C.byref(_desc(outs[2])), _stream(stream)))
+    return tuple(outs)
+
+
+# ----------------------------------------------------------------------------- time to contact
+def decode_levels(buf: torch.Tensor) -> np.ndarray:
+    """tc_ttc_level records (device bytes) -> numpy structured array."""
+    return buf.cpu().numpy().view(L.LEVEL_DTYPE)
+
+
+def decode_picks(buf: torch.Tensor) -> np.ndarray:
+    return buf.cpu().numpy().view(L.PICK_DTYPE)
+
+
+def ttc_workspace_size(H: int, W: int, levels: int) -> int:
+    n = C.c_size_t(0)
+    L.check("tc_ttc_workspace_size", _lib().tc_ttc_workspace_size(H, W, levels, C.byref(n)))
+    return n.value
+
+
+def ttc_solve(prev: torch.Tensor, nxt: torch.Tensor, levels: int = 1, ws: Optional[torch.Tensor] = None,
+              out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, stream=None):
+    """One frame pair -> (levels buffer [levels*152 B], pick buffer [56 B]) on the device."""
+    lib = _lib()
+    H, W = prev.shape
+    nbytes = ttc_workspace_size(H, W, levels)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=prev.device)
+    if out is None:
+        out = (torch.empty(levels * L.LEVEL_DTYPE.itemsize, dtype=torch.uint8, device=prev.device),
+               torch.empty(L.PICK_DTYPE.itemsize, dtype=torch.uint8, device=prev.device))
+    L.check("tc_ttc_solve", lib.tc_ttc_solve(C.byref(_desc(prev)), C.byref(_desc(nxt)), levels, C.c_void_p(ws.data_ptr()),
+                                             ws.numel(), C.c_void_p(out[0].data_ptr()), C.c_void_p(out[1].data_ptr()),
+                                             _stream(stream)))
+    return out
+
+
+def seq_from_frames(frames: torch.Tensor, levels: int) -> L.TcSeq:
+    """A [F, H, W] u8/f16 video tensor (row-contiguous) as a tc_seq descriptor."""
+    if frames.dim() != 3 or frames.stride(2) != 1:
+        raise ValueError("frames must be [F, H, W] with contiguous rows")
+    q = L.TcSeq()
+    q.frame0 = frames.data_ptr()
+    q.frame_stride = frames.stride(0)
+    q.row_stride = frames.stride(1)
+    q.H, q.W = int(frames.shape[1]), int(frames.shape[2])
+    q.n_frames = int(frames.shape[0])
+    q.levels = levels
+    return q
+
+
+def seq_from_pair(prev: torch.Tensor, nxt: torch.Tensor, levels: int) -> L.TcSeq:
+    """Two unrelated frames as a 2-frame stream (frame_stride = next - prev)."""
+    es = prev.element_size()
+    diff = nxt.data_ptr() - prev.data_ptr()
+    if diff % es:
+        raise ValueError("frames are not element-aligned relative to each other")
+    q = L.TcSeq()
+    q.frame0 = prev.data_ptr()
+    q.frame_stride = diff // es
+    q.row_stride = prev.stride(0)
+    q.H, q.W = int(prev.shape[0]), int(prev.shape[1])
+    q.n_frames = 2
+    q.levels = levels
+    return q
+
+
+class TTCPlan:
+    """A batch of streams planned once and run many times (graph-capturable run)."""
+
+    def __init__(self, seqs: Sequence[L.TcSeq], dtype: torch.dtype, device=None, keep: Sequence = ()):
+        self._lib = _lib()
+        self._keep = list(keep)  # tensors the descriptors point into
+        arr = (L.TcSeq * len(seqs))(*seqs)
+        h = C.c_void_p()
+        L.check("tc_ttc_plan_create", self._lib.tc_ttc_plan_create(arr, len(seqs), _DT[dtype], C.byref(h)))
+        self._h = h
+        ws = C.c_size_t(0)
+        npairs = C.c_int64(0)
+        nrec = C.c_int64(0)
+        L.check("tc_ttc_plan_info", self._lib.tc_ttc_plan_info(h, C.byref(ws), C.byref(npairs), C.byref(nrec)))
+        self.ws_bytes = ws.value
+        self.n_pairs = npairs.value
+        self.n_records = nrec.value
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(max(1, self.ws_bytes), dtype=torch.uint8, device=dev)
+        self.levels_buf = torch.empty(max(1, self.n_records) * L.LEVEL_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self.picks_buf = torch.empty(max(1, self.n_pairs) * L.PICK_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self.uploaded = False
+
+    def upload(self, stream=None):
+        L.check("tc_ttc_plan_upload", self._lib.tc_ttc_plan_upload(self._h, C.c_void_p(self.ws.data_ptr()),
+                                                                   self.ws.numel(), _stream(stream)))
+        self.uploaded = True
+
+    def run(self, stream=None):
+        if not self.uploaded:
+            self.upload(stream)
+        L.check("tc_ttc_plan_run", self._lib.tc_ttc_plan_run(self._h, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                             C.c_void_p(self.levels_buf.data_ptr()),
+                                                             C.c_void_p(self.picks_buf.data_ptr()), _stream(stream)))
+
+    def run_phase(self, phase: int, stream=None):
+        """Phase 1: fused pass only; phase 2: finishing pass only; 3: both."""
+        if not self.uploaded:
+            self.upload(stream)
+        L.check("tc_ttc_plan_run_phase",
+                self._lib.tc_ttc_plan_run_phase(self._h, C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                                C.c_void_p(self.levels_buf.data_ptr()),
+                                                C.c_void_p(self.picks_buf.data_ptr()), phase, _stream(stream)))
+
+    def results(self):
+        return decode_levels(self.levels_buf[: self.n_records * L.LEVEL_DTYPE.itemsize]), \
+            decode_picks(self.picks_buf[: self.n_pairs * L.PICK_DTYPE.itemsize])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.tc_ttc_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ttc_solve_batched(videos: Sequence[torch.Tensor], levels: int, stream=None):
+    """Every consecutive pair of every [F, H, W] video -> (levels records, picks) as numpy arrays."""
+    dtype = videos[0].dtype
+    plan = TTCPlan([seq_from_frames(v, levels) for v in videos], dtype, videos[0].device, keep=videos)
+    plan.run(stream)
+    torch.cuda.synchronize()
+    out = plan.results()
+    plan.close()
+    return out

@@ -1,0 +1,86 @@
+// Host-side declarations shared by the C ABI (ttcconv.cpp) and the kernel
+// launchers (*.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ttcconv.h"
+
+namespace ttc {
+
+// ---------------------------------------------------------------- convolution
+struct ConvND {
+  int ndim;
+  int xdt;                      // TC_F32, TC_F16 or TC_U8
+  const void* x;
+  int64_t xshape[TC_MAX_DIMS];
+  int64_t xstride[TC_MAX_DIMS];
+  const void* k;                // contiguous, F32 or I32
+  int64_t kshape[TC_MAX_DIMS];
+  void* y;                      // F32 or I32
+  int64_t yshape[TC_MAX_DIMS];
+  int64_t ystride[TC_MAX_DIMS];
+  int64_t off[TC_MAX_DIMS];     // output index n maps to full index n + off
+};
+
+// Chooses a kernel (2-D tiled, 3-D tiled, or generic rank-n) and launches it.
+hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s);
+
+// ---------------------------------------------------------------- pyramid / derivatives
+struct Image2D {
+  const void* p;
+  int dt;
+  int64_t s0, s1;  // strides (elements)
+};
+
+hipError_t launch_pyramid_level(const Image2D& src, float* dst, int64_t d0, int64_t d1, int Ho, int Wo,
+                                hipStream_t s);
+hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, void* ex, void* ey, void* et,
+                       int odt, const int64_t* os0, const int64_t* os1, hipStream_t s);
+
+// ---------------------------------------------------------------- fused TTC
+// One entry of the device work table: a video stream and where its work and
+// results go.  The fused pass covers the stream with "items": a group of four
+// vertically adjacent bands (one per wave) of kRowsPerBand rows by one
+// column-wave of 480 owned base columns (4 segments x 15 lanes x 8 columns).
+struct SeqDesc {
+  const void* frame0;
+  int64_t frame_stride;   // elements
+  int64_t row_stride;     // elements
+  int32_t H, W;
+  int32_t n_frames;
+  int32_t levels;
+  int32_t band_rows;      // owned base rows per band (one wave)
+  int32_t n_bands;        // ceil(H / band_rows)
+  int32_t n_bgroups;      // ceil(n_bands / 4)
+  int32_t n_cw;           // ceil(ceil((W - 1) / 120) / 4)
+  int64_t item_begin;     // first work item of this stream (prefix over streams)
+  int64_t pair_begin;     // first global pair index of this stream
+  int64_t partial_begin;  // first float of this stream's partial sums
+  int32_t n_witems;       // wave items per (pair, level) = n_bgroups * n_cw * 4
+  int32_t vec;            // 1: every 8-pixel lane chunk is aligned for one vector load
+};
+
+constexpr int kSegCols = 120;         // owned base columns per 16-lane segment
+constexpr int kWaveCols = 4 * kSegCols;
+constexpr int kWavesPerItem = 4;
+
+struct FusedLaunch {
+  int dt;           // TC_U8 or TC_F16
+  int levels;       // 1..4
+  int band_rows;    // 8, 16 or 24
+  const SeqDesc* table;  // device table, or nullptr to use `inl`
+  int n_seqs;
+  SeqDesc inl;
+  int64_t n_items;
+  int64_t n_pairs;
+  float* partials;
+  int grid;         // persistent grid size (work-groups)
+};
+
+hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_finish(const FusedLaunch& f, tc_ttc_level* out, tc_ttc_pick* picks, hipStream_t s);
+bool fused_variant_exists(int dt, int levels, int band_rows);
+
+}  // namespace ttc

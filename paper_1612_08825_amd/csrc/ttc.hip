@@ -1,0 +1,534 @@
+// Fused multi-scale time-to-contact pass for gfx950.
+//
+// What is computed (Time to Contact, Formulation and Results): for every
+// consecutive frame pair of a stream and every pyramid level l < LV, the ten
+// sums of the least-squares normal equations over all 2x2x2 first-difference
+// cubes of that level; then the FP64 3x3 solve, FOE, TTC and the multi-scale
+// level choice.
+//
+// How (one persistent launch, then a small finishing launch):
+//   * A wave owns a band of kRowsPerBand base rows and 480 columns, split in
+//     four 16-lane segments; lane i of a segment holds 8 adjacent base
+//     columns (one level-3 column).  Lane 15 of each segment only provides its
+//     left column to lane 14 (the segment owns 120 columns).
+//   * The wave walks the stream's frames in time.  The previous frame's band
+//     stays in registers in its packed u8 / f16 form, so every frame is read
+//     from memory once; each new frame row is combined with the stored one as
+//     the temporal sum S = P0 + P1 and difference D = P1 - P0.
+//   * Rows are walked top to bottom.  Horizontal neighbour sums/differences of
+//     S and D give the derivative cube by one more vertical step.  Because the
+//     pyramid is linear, the 2x2 sums of S and D at even columns *are* the next
+//     level's S and D (times 4), so all levels are built on the fly in
+//     registers; nothing is written but the sums.  Values are kept as
+//     un-normalised block sums; the powers of two are removed in FP64 at the end.
+//   * The walk continues 2^(LV-1) rows past the band (halo) so that the last
+//     owned cube row of every level has its lower neighbour.
+//   * Per pair each lane sums its cubes in FP32; the wave reduces its lanes with
+//     DPP and writes one partial per (pair, level, wave).  The finishing pass
+//     combines the partials of a pair in a fixed order with TwoSum (hi, lo)
+//     compensation, converts to FP64, solves and selects the level.
+//
+// Units inside the kernel at level l (U = block sums of 4^l base pixels of S or D):
+//   hx = 2^(3l+2) E_x (per base px), hy likewise, ht = 2^(2l+2) E_t,
+//   g = x_l hx + y_l hy = 2^(2l+2) G with x_l, y_l the cube centre in level pixels.
+#include <math.h>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+
+namespace ttc {
+namespace {
+
+struct FusedArgs {
+  const SeqDesc* table;
+  int n_seqs;
+  SeqDesc inl;
+  int64_t n_items;
+  int64_t n_pairs;
+  float* partials;
+};
+
+__device__ __forceinline__ SeqDesc seq_for_item(const FusedArgs& a, int64_t item) {
+  if (a.table == nullptr) return a.inl;
+  int lo = 0, hi = a.n_seqs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.table[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  return a.table[lo];
+}
+
+__device__ __forceinline__ SeqDesc seq_for_pair(const FusedArgs& a, int64_t pair) {
+  if (a.table == nullptr) return a.inl;
+  int lo = 0, hi = a.n_seqs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.table[mid].pair_begin <= pair) lo = mid; else hi = mid - 1;
+  }
+  return a.table[lo];
+}
+
+// Accumulate the cubes of one row of one level.  hd*, hs*, hD* are the horizontal
+// quantities of the previous (p) and current level rows.  EDGE: some lane of the
+// wave has a partial set of valid columns at this level.
+template <int NC, bool EDGE>
+__device__ __forceinline__ void cubes(float (&acc)[10], const float (&hdp)[NC], const float (&hd)[NC],
+                                      const float (&hsp)[NC], const float (&hs)[NC], const float (&hDp)[NC],
+                                      const float (&hD)[NC], int ncv, float xb, float y) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (!EDGE || c < ncv) {
+      const float ex = hdp[c] + hd[c];
+      const float ey = hs[c] - hsp[c];
+      const float et = hDp[c] + hD[c];
+      const float g = fmaf(y, ey, (xb + (float)c) * ex);
+      acc[0] = fmaf(ex, ex, acc[0]);
+      acc[1] = fmaf(ex, ey, acc[1]);
+      acc[2] = fmaf(ey, ey, acc[2]);
+      acc[3] = fmaf(g, ex, acc[3]);
+      acc[4] = fmaf(g, ey, acc[4]);
+      acc[5] = fmaf(g, g, acc[5]);
+      acc[6] = fmaf(ex, et, acc[6]);
+      acc[7] = fmaf(ey, et, acc[7]);
+      acc[8] = fmaf(g, et, acc[8]);
+      acc[9] = fmaf(et, et, acc[9]);
+    }
+  }
+}
+
+template <int NC>
+__device__ __forceinline__ void cubes_dispatch(bool edge, float (&acc)[10], const float (&hdp)[NC],
+                                               const float (&hd)[NC], const float (&hsp)[NC], const float (&hs)[NC],
+                                               const float (&hDp)[NC], const float (&hD)[NC], int ncv, float xb,
+                                               float y) {
+  if (edge) cubes<NC, true>(acc, hdp, hd, hsp, hs, hDp, hD, ncv, xb, y);
+  else cubes<NC, false>(acc, hdp, hd, hsp, hs, hDp, hD, ncv, xb, y);
+}
+
+// Horizontal quantities of one level row of NC columns, given its block sums U
+// (of S) and V (of D); the column right of the lane comes from lane + 1.
+template <int NC>
+__device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&V)[NC], float (&hs)[NC],
+                                            float (&hd)[NC], float (&hD)[NC]) {
+  const float un = __shfl_down(U[0], 1, 16);
+  const float vn = __shfl_down(V[0], 1, 16);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const float ur = (c + 1 < NC) ? U[c + 1] : un;
+    const float vr = (c + 1 < NC) ? V[c + 1] : vn;
+    hs[c] = U[c] + ur;
+    hd[c] = ur - U[c];
+    hD[c] = V[c] + vr;
+  }
+}
+
+template <typename T, int LV, int RH>
+__global__ __launch_bounds__(256) void ttc_fused(FusedArgs a) {
+  constexpr int HALO = 1 << (LV - 1);
+  constexpr int NR = RH + HALO;  // rows walked per band
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int li = lane & 15;
+  const int seg = lane >> 4;
+
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so give
+  // each XCD a contiguous run of items (vertically adjacent bands share halos).
+  const int64_t slot = (G % 8 == 0) ? (int64_t)(g % 8) * (G / 8) + g / 8 : g;
+
+  for (int64_t t = 0;; ++t) {
+    const int64_t item = t * G + slot;
+    if (item >= a.n_items) break;
+    const SeqDesc d = seq_for_item(a, item);
+    const int64_t local = item - d.item_begin;
+    const int cw = (int)(local / d.n_bgroups);
+    const int bg = (int)(local % d.n_bgroups);
+    const int band = bg * kWavesPerItem + wave;
+    const int64_t witem = local * kWavesPerItem + wave;
+    const int n_pairs = d.n_frames - 1;
+    float* part = a.partials + d.partial_begin;
+
+    if (band >= d.n_bands) {  // empty wave of the last band group: zero partials
+      for (int p = 0; p < n_pairs; ++p)
+        for (int l = 0; l < LV; ++l)
+          if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = 0.f;
+      continue;
+    }
+
+    const int H = d.H, W = d.W;
+    const int row0 = band * RH;
+    const int c_lane = cw * kWaveCols + seg * kSegCols + li * 8;
+
+    // valid cube columns of this lane per level, and the cube-centre bases
+    int ncv[LV];
+    float xb[LV], yb[LV];
+    bool edge[LV];
+#pragma unroll
+    for (int l = 0; l < LV; ++l) {
+      const int wl = W >> l;
+      const int j0 = c_lane >> l;
+      int n = wl - 1 - j0;
+      n = n < 0 ? 0 : (n > (8 >> l) ? (8 >> l) : n);
+      ncv[l] = (li == 15) ? 0 : n;
+      xb[l] = (float)(j0 + 1) - (float)W / (float)(2 << l);
+      yb[l] = (float)(row0 >> l) - (float)H / (float)(2 << l);
+      const bool part_lane = ncv[l] > 0 && ncv[l] < (8 >> l);
+      edge[l] = __any(part_lane);
+    }
+
+    const T* f0 = reinterpret_cast<const T*>(d.frame0);
+    const int ncols = W - c_lane;  // pixels of this lane inside the image
+    const bool vec = d.vec != 0;  // uniform: 8-pixel chunks are 8/16-byte aligned
+    auto load_row = [&](Raw8<T>& r, const T* frame, int row) {
+      const T* p = frame + (int64_t)row * d.row_stride + c_lane;
+      if (vec && ncols >= 8) r.load(p);
+      else if (ncols > 0) r.load_partial(p, ncols < 8 ? ncols : 8);
+      else r.zero();
+    };
+
+    Raw8<T> prv[NR];
+#pragma unroll
+    for (int w = 0; w < NR; ++w) {
+      if (row0 + w < H) load_row(prv[w], f0, row0 + w);
+      else prv[w].zero();
+    }
+
+    for (int k = 1; k < d.n_frames; ++k) {
+      const T* fk = f0 + (int64_t)k * d.frame_stride;
+      float acc[LV][10];
+#pragma unroll
+      for (int l = 0; l < LV; ++l)
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[l][q] = 0.f;
+
+      float hs0p[8], hd0p[8], hD0p[8];
+      float hs1p[4], hd1p[4], hD1p[4];
+      float hs2p[2], hd2p[2], hD2p[2];
+      float hs3p[1], hd3p[1], hD3p[1];
+
+#pragma unroll
+      for (int w = 0; w < NR; ++w) {
+        if (row0 + w < H) {
+          Raw8<T> cur;
+          load_row(cur, fk, row0 + w);
+          float pa[8], pb[8];
+          prv[w].unpack(pa);
+          cur.unpack(pb);
+          prv[w] = cur;
+          float S[8], D[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            S[c] = pa[c] + pb[c];
+            D[c] = pb[c] - pa[c];
+          }
+          float hs0[8], hd0[8], hD0[8];
+          horizontals<8>(S, D, hs0, hd0, hD0);
+          if (w >= 1 && w <= RH)
+            cubes_dispatch<8>(edge[0], acc[0], hd0p, hd0, hs0p, hs0, hD0p, hD0, ncv[0], xb[0], yb[0] + (float)w);
+          if constexpr (LV >= 2) {
+            if ((w & 1) == 1) {
+              float U1[4], V1[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                U1[c] = hs0p[2 * c] + hs0[2 * c];
+                V1[c] = hD0p[2 * c] + hD0[2 * c];
+              }
+              float hs1[4], hd1[4], hD1[4];
+              horizontals<4>(U1, V1, hs1, hd1, hD1);
+              constexpr int r1 = 0;  // placeholder to keep the structure readable
+              (void)r1;
+              const int lr1 = w >> 1;
+              if (lr1 >= 1 && lr1 <= (RH >> 1))
+                cubes_dispatch<4>(edge[1], acc[1], hd1p, hd1, hs1p, hs1, hD1p, hD1, ncv[1], xb[1],
+                                  yb[1] + (float)lr1);
+              if constexpr (LV >= 3) {
+                if ((w & 3) == 3) {
+                  float U2[2], V2[2];
+#pragma unroll
+                  for (int c = 0; c < 2; ++c) {
+                    U2[c] = hs1p[2 * c] + hs1[2 * c];
+                    V2[c] = hD1p[2 * c] + hD1[2 * c];
+                  }
+                  float hs2[2], hd2[2], hD2[2];
+                  horizontals<2>(U2, V2, hs2, hd2, hD2);
+                  const int lr2 = w >> 2;
+                  if (lr2 >= 1 && lr2 <= (RH >> 2))
+                    cubes_dispatch<2>(edge[2], acc[2], hd2p, hd2, hs2p, hs2, hD2p, hD2, ncv[2], xb[2],
+                                      yb[2] + (float)lr2);
+                  if constexpr (LV >= 4) {
+                    if ((w & 7) == 7) {
+                      float U3[1], V3[1];
+                      U3[0] = hs2p[0] + hs2[0];
+                      V3[0] = hD2p[0] + hD2[0];
+                      float hs3[1], hd3[1], hD3[1];
+                      horizontals<1>(U3, V3, hs3, hd3, hD3);
+                      const int lr3 = w >> 3;
+                      if (lr3 >= 1 && lr3 <= (RH >> 3))
+                        cubes_dispatch<1>(edge[3], acc[3], hd3p, hd3, hs3p, hs3, hD3p, hD3, ncv[3], xb[3],
+                                          yb[3] + (float)lr3);
+                      hs3p[0] = hs3[0];
+                      hd3p[0] = hd3[0];
+                      hD3p[0] = hD3[0];
+                    }
+                  }
+#pragma unroll
+                  for (int c = 0; c < 2; ++c) {
+                    hs2p[c] = hs2[c];
+                    hd2p[c] = hd2[c];
+                    hD2p[c] = hD2[c];
+                  }
+                }
+              }
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                hs1p[c] = hs1[c];
+                hd1p[c] = hd1[c];
+                hD1p[c] = hD1[c];
+              }
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            hs0p[c] = hs0[c];
+            hd0p[c] = hd0[c];
+            hD0p[c] = hD0[c];
+          }
+        }
+      }
+
+      // one partial per (pair, level, wave): lanes that own no cube of a level
+      // contribute zero; lanes 0..9 store sum q = lane
+      const int p = k - 1;
+#pragma unroll
+      for (int l = 0; l < LV; ++l) {
+        const bool own = ncv[l] > 0;
+        float mine = 0.f;
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+          const float v = wave64_allreduce(own ? acc[l][q] : 0.f);
+          mine = (lane == q) ? v : mine;
+        }
+        if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = mine;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finishing pass
+__device__ __forceinline__ int sum_scale_exp(int l, int q) {
+  // hx, hy carry 2^(3l+2), g and ht carry 2^(2l+2)
+  switch (q) {
+    case 0: case 1: case 2: return 6 * l + 4;
+    case 3: case 4: case 6: case 7: return 5 * l + 4;
+    default: return 4 * l + 4;
+  }
+}
+
+#pragma clang fp contract(off)
+__device__ void solve_level(const double* s, tc_ttc_level& r) {
+  const double nan = __builtin_nan("");
+  for (int q = 0; q < TC_NUM_SUMS; ++q) r.sums[q] = s[q];
+  r.A = r.B = r.C = r.ttc = r.x0 = r.y0 = r.resid = nan;
+  r.status = TC_OK;
+  for (int q = 0; q < TC_NUM_SUMS; ++q)
+    if (!isfinite(s[q])) {
+      r.status = TC_NONFINITE;
+      return;
+    }
+  double M[3][4] = {{s[0], s[1], s[3], -s[6]}, {s[1], s[2], s[4], -s[7]}, {s[3], s[4], s[5], -s[8]}};
+  if (M[0][0] <= 0.0 || M[1][1] <= 0.0 || M[2][2] <= 0.0) {
+    r.status = TC_SINGULAR;
+    return;
+  }
+  double dg[3];
+  for (int i = 0; i < 3; ++i) dg[i] = 1.0 / sqrt(M[i][i]);
+  double a[3][4];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) a[i][j] = dg[i] * M[i][j] * dg[j];
+    a[i][3] = dg[i] * M[i][3];
+  }
+  double minpiv = 1e300;
+  for (int c = 0; c < 3; ++c) {
+    int p = c;
+    for (int i = c + 1; i < 3; ++i)
+      if (fabs(a[i][c]) > fabs(a[p][c])) p = i;
+    if (p != c)
+      for (int j = 0; j < 4; ++j) {
+        const double t = a[c][j];
+        a[c][j] = a[p][j];
+        a[p][j] = t;
+      }
+    const double piv = a[c][c];
+    minpiv = fmin(minpiv, fabs(piv));
+    if (piv == 0.0) break;
+    for (int i = c + 1; i < 3; ++i) {
+      const double f = a[i][c] / piv;
+      for (int j = c; j < 4; ++j) a[i][j] = a[i][j] - f * a[c][j];
+    }
+  }
+  if (!(minpiv >= 1e-6)) {
+    r.status = TC_SINGULAR;
+    return;
+  }
+  double v[3];
+  for (int i = 2; i >= 0; --i) {
+    double acc = a[i][3];
+    for (int j = i + 1; j < 3; ++j) acc = acc - a[i][j] * v[j];
+    v[i] = acc / a[i][i];
+  }
+  const double A = dg[0] * v[0], B = dg[1] * v[1], C = dg[2] * v[2];
+  r.A = A;
+  r.B = B;
+  r.C = C;
+  if (C == 0.0) {
+    r.ttc = copysign(__builtin_inf(), C);
+  } else {
+    r.ttc = 1.0 / C;
+    r.x0 = -A / C;
+    r.y0 = -B / C;
+  }
+  r.resid = s[9] + A * s[6] + B * s[7] + C * s[8];
+}
+#pragma clang fp contract(on)
+
+__device__ __forceinline__ double level_key(const tc_ttc_level& r) {
+  if (r.status != TC_OK || !isfinite(r.ttc) || !(r.ttc > 0.0)) return __builtin_inf();
+  return r.ttc;
+}
+
+template <int LV>
+__global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __restrict__ out,
+                                                  tc_ttc_pick* __restrict__ picks) {
+  const int64_t gp = blockIdx.x;
+  if (gp >= a.n_pairs) return;
+  const SeqDesc d = seq_for_pair(a, gp);
+  const int64_t p = gp - d.pair_begin;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ float red_hi[4][10], red_lo[4][10];
+  __shared__ double sums[LV][10];
+  __shared__ tc_ttc_level res[LV];
+
+  for (int l = 0; l < LV; ++l) {
+    float hi[10], lo[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) hi[q] = lo[q] = 0.f;
+    const float* base = a.partials + d.partial_begin + (p * LV + l) * (int64_t)d.n_witems * 10;
+    for (int w = tid; w < d.n_witems; w += 256) {
+#pragma unroll
+      for (int q = 0; q < 10; ++q) comp_add(hi[q], lo[q], base[(int64_t)w * 10 + q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+#pragma unroll
+      for (int m = 1; m < 64; m <<= 1) {
+        const float h2 = __shfl_xor(hi[q], m, 64);
+        const float l2 = __shfl_xor(lo[q], m, 64);
+        comp_merge(hi[q], lo[q], h2, l2);
+      }
+    }
+    if (lane == 0)
+      for (int q = 0; q < 10; ++q) {
+        red_hi[wave][q] = hi[q];
+        red_lo[wave][q] = lo[q];
+      }
+    __syncthreads();
+    if (tid < 10) {
+      float h = red_hi[0][tid], lo0 = red_lo[0][tid];
+      for (int wv = 1; wv < 4; ++wv) comp_merge(h, lo0, red_hi[wv][tid], red_lo[wv][tid]);
+      sums[l][tid] = ldexp((double)h + (double)lo0, -sum_scale_exp(l, tid));
+    }
+    __syncthreads();
+  }
+
+  if (tid < LV) {
+    tc_ttc_level r;
+    solve_level(sums[tid], r);
+    const int64_t Hl = d.H >> tid, Wl = d.W >> tid;
+    r.n = (Hl - 1) * (Wl - 1);
+    r.level = tid;
+    res[tid] = r;
+    out[gp * LV + tid] = r;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int l = 0;
+    while (l + 1 < LV && level_key(res[l + 1]) < level_key(res[l])) ++l;
+    tc_ttc_pick pk;
+    pk.ttc = res[l].ttc;
+    pk.x0 = res[l].x0;
+    pk.y0 = res[l].y0;
+    pk.A = res[l].A;
+    pk.B = res[l].B;
+    pk.C = res[l].C;
+    pk.level = l;
+    pk.status = res[l].status;
+    picks[gp] = pk;
+  }
+}
+
+FusedArgs make_args(const FusedLaunch& f) {
+  FusedArgs a;
+  a.table = f.table;
+  a.n_seqs = f.n_seqs;
+  a.inl = f.inl;
+  a.n_items = f.n_items;
+  a.n_pairs = f.n_pairs;
+  a.partials = f.partials;
+  return a;
+}
+
+template <typename T, int LV>
+hipError_t fused_rh(const FusedLaunch& f, hipStream_t s) {
+  const FusedArgs a = make_args(f);
+  const dim3 grid((unsigned)f.grid), block(256);
+  switch (f.band_rows) {
+    case 8: hipLaunchKernelGGL((ttc_fused<T, LV, 8>), grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL((ttc_fused<T, LV, 16>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fused_lv(const FusedLaunch& f, hipStream_t s) {
+  switch (f.levels) {
+    case 1: return fused_rh<T, 1>(f, s);
+    case 2: return fused_rh<T, 2>(f, s);
+    case 3: return fused_rh<T, 3>(f, s);
+    case 4: return fused_rh<T, 4>(f, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool fused_variant_exists(int dt, int levels, int band_rows) {
+  return (dt == TC_U8 || dt == TC_F16) && levels >= 1 && levels <= 4 && (band_rows == 8 || band_rows == 16) &&
+         band_rows >= (1 << (levels - 1));
+}
+
+hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s) {
+  if (f.n_items == 0) return hipSuccess;
+  switch (f.dt) {
+    case TC_U8: return fused_lv<uint8_t>(f, s);
+    case TC_F16: return fused_lv<_Float16>(f, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_ttc_finish(const FusedLaunch& f, tc_ttc_level* out, tc_ttc_pick* picks, hipStream_t s) {
+  if (f.n_pairs == 0) return hipSuccess;
+  const FusedArgs a = make_args(f);
+  const dim3 grid((unsigned)f.n_pairs), block(256);
+  switch (f.levels) {
+    case 1: hipLaunchKernelGGL(ttc_finish<1>, grid, block, 0, s, a, out, picks); break;
+    case 2: hipLaunchKernelGGL(ttc_finish<2>, grid, block, 0, s, a, out, picks); break;
+    case 3: hipLaunchKernelGGL(ttc_finish<3>, grid, block, 0, s, a, out, picks); break;
+    case 4: hipLaunchKernelGGL(ttc_finish<4>, grid, block, 0, s, a, out, picks); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ttc

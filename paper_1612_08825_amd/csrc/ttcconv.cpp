@@ -1,0 +1,536 @@
+// Host side of the C ABI declared in include/ttcconv.h: argument validation,
+// work planning for the fused TTC pass, and kernel dispatch.  No device memory
+// is allocated here; the only host allocations are plan objects (pinned work
+// tables) and the small tap copy of integer convolutions.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace ttc;
+
+namespace {
+
+constexpr int kVersion = 100;  // 0.1.0
+
+int elem_size(int dt) {
+  switch (dt) {
+    case TC_U8: return 1;
+    case TC_F16: return 2;
+    case TC_F32: return 4;
+    case TC_I32: return 4;
+    case TC_F64: return 8;
+    default: return 0;
+  }
+}
+
+int64_t numel(const tc_tensor* t) {
+  int64_t n = 1;
+  for (int d = 0; d < t->ndim; ++d) n *= t->shape[d];
+  return n;
+}
+
+// Basic structural checks of a descriptor.
+int check_tensor(const tc_tensor* t, bool need_data) {
+  if (!t) return TC_EINVAL;
+  if (t->ndim < 1 || t->ndim > TC_MAX_DIMS) return TC_ESHAPE;
+  if (elem_size(t->dtype) == 0) return TC_EDTYPE;
+  for (int d = 0; d < t->ndim; ++d) {
+    if (t->shape[d] < 0 || t->shape[d] > (1LL << 40)) return TC_ESHAPE;
+    if (t->shape[d] > 1 && t->stride[d] == 0) return TC_ESHAPE;
+  }
+  if (need_data && numel(t) > 0 && t->data == nullptr) return TC_EINVAL;
+  return TC_OK;
+}
+
+bool is_contiguous(const tc_tensor* t) {
+  int64_t s = 1;
+  for (int d = t->ndim - 1; d >= 0; --d) {
+    if (t->shape[d] > 1 && t->stride[d] != s) return false;
+    s *= t->shape[d];
+  }
+  return true;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? TC_OK : TC_EDEVICE; }
+
+int conv_dtypes_ok(int xdt, int kdt) {
+  if (xdt == TC_F32 && kdt == TC_F32) return TC_F32;
+  if (xdt == TC_F16 && kdt == TC_F32) return TC_F32;
+  if (xdt == TC_U8 && kdt == TC_I32) return TC_I32;
+  return -1;
+}
+
+int conv_geometry(const tc_tensor* x, const tc_tensor* k, int32_t mode, int64_t* out_shape, int64_t* off) {
+  if (x->ndim != k->ndim) return TC_ESHAPE;
+  const int r = x->ndim;
+  if (mode == TC_FULL) {
+    for (int d = 0; d < r; ++d) {
+      out_shape[d] = x->shape[d] + k->shape[d] - 1;
+      if (x->shape[d] == 0 || k->shape[d] == 0) out_shape[d] = 0;
+      off[d] = 0;
+    }
+  } else if (mode == TC_SAME) {
+    for (int d = 0; d < r; ++d) {
+      out_shape[d] = x->shape[d];
+      off[d] = (k->shape[d] - 1) / 2;
+      if (k->shape[d] == 0) out_shape[d] = 0;
+    }
+  } else if (mode == TC_VALID) {
+    bool ge = true, le = true;
+    for (int d = 0; d < r; ++d) {
+      ge = ge && x->shape[d] >= k->shape[d];
+      le = le && x->shape[d] <= k->shape[d];
+    }
+    if (!ge && !le) return TC_ESHAPE;
+    for (int d = 0; d < r; ++d) {
+      const int64_t n = x->shape[d], m = k->shape[d];
+      out_shape[d] = (n == 0 || m == 0) ? 0 : (n > m ? n - m : m - n) + 1;
+      off[d] = std::min(n, m) - 1;
+      if (off[d] < 0) off[d] = 0;
+    }
+  } else {
+    return TC_EINVAL;
+  }
+  return TC_OK;
+}
+
+int current_cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+}  // namespace
+
+// ============================================================================ misc
+extern "C" const char* tc_status_str(int status) {
+  switch (status) {
+    case TC_OK: return "ok";
+    case TC_SINGULAR: return "singular normal matrix";
+    case TC_NEED_PREV: return "no previous frame";
+    case TC_NONFINITE: return "non-finite sums";
+    case TC_EINVAL: return "invalid argument";
+    case TC_ESHAPE: return "inconsistent shape or stride";
+    case TC_EDTYPE: return "unsupported dtype";
+    case TC_EOVERFLOW: return "integer result could overflow int32";
+    case TC_ENOMEM: return "workspace too small";
+    case TC_EDEVICE: return "HIP error or unsupported device";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int tc_version(void) { return kVersion; }
+
+extern "C" int tc_device_check(int device, int* n_cu) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TC_EDEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TC_EDEVICE;
+  if (n_cu) *n_cu = prop.multiProcessorCount;
+  return TC_OK;
+}
+
+// ============================================================================ convolution
+extern "C" int tc_conv_out_shape(const tc_tensor* x, const tc_tensor* k, int32_t mode, int64_t* out_shape) {
+  int st;
+  if ((st = check_tensor(x, false)) != TC_OK) return st;
+  if ((st = check_tensor(k, false)) != TC_OK) return st;
+  if (!out_shape) return TC_EINVAL;
+  if (conv_dtypes_ok(x->dtype, k->dtype) < 0) return TC_EDTYPE;
+  int64_t off[TC_MAX_DIMS];
+  return conv_geometry(x, k, mode, out_shape, off);
+}
+
+extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* stream) {
+  int st;
+  if ((st = check_tensor(x, true)) != TC_OK) return st;
+  if ((st = check_tensor(k, true)) != TC_OK) return st;
+  if ((st = check_tensor(y, true)) != TC_OK) return st;
+  const int ydt = conv_dtypes_ok(x->dtype, k->dtype);
+  if (ydt < 0 || y->dtype != ydt) return TC_EDTYPE;
+  if (!is_contiguous(k)) return TC_ESHAPE;
+  const int64_t ktaps = numel(k);
+  if (ktaps > (1LL << 20)) return TC_EINVAL;
+  int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
+  if ((st = conv_geometry(x, k, mode, oshape, off)) != TC_OK) return st;
+  if (y->ndim != x->ndim) return TC_ESHAPE;
+  for (int d = 0; d < y->ndim; ++d)
+    if (y->shape[d] != oshape[d]) return TC_ESHAPE;
+  if (numel(y) == 0) return TC_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+  bool small_taps = true;
+  if (k->dtype == TC_I32) {
+    // exactness bound: every partial sum is at most 255 * sum|k| in magnitude
+    std::vector<int32_t> kh((size_t)ktaps);
+    if (ktaps > 0) {
+      if (hipMemcpyAsync(kh.data(), k->data, (size_t)ktaps * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return TC_EDEVICE;
+      if (hipStreamSynchronize(s) != hipSuccess) return TC_EDEVICE;
+    }
+    int64_t sabs = 0;
+    for (int32_t v : kh) {
+      const int64_t a = v < 0 ? -(int64_t)v : (int64_t)v;
+      sabs += a;
+      if (a >= (1LL << 23)) small_taps = false;
+    }
+    if (255 * sabs > 2147483647LL) return TC_EOVERFLOW;
+  }
+  // zero-size x: the result is all zeros in full/same mode
+  if (numel(x) == 0 || ktaps == 0) {
+    if (is_contiguous(y)) return hip_status(hipMemsetAsync(y->data, 0, (size_t)numel(y) * 4, s));
+    return TC_ESHAPE;
+  }
+
+  ConvND c{};
+  c.ndim = x->ndim;
+  c.xdt = x->dtype;
+  c.x = x->data;
+  c.k = k->data;
+  c.y = y->data;
+  for (int d = 0; d < c.ndim; ++d) {
+    c.xshape[d] = x->shape[d];
+    c.xstride[d] = x->stride[d];
+    c.kshape[d] = k->shape[d];
+    c.yshape[d] = y->shape[d];
+    c.ystride[d] = y->stride[d];
+    c.off[d] = off[d];
+  }
+  return hip_status(launch_conv(c, small_taps, s));
+}
+
+// ============================================================================ pyramid / derivatives
+extern "C" int tc_pyramid_shape(int64_t H, int64_t W, int32_t level, int64_t* Hl, int64_t* Wl) {
+  if (H < 0 || W < 0 || level < 0 || level > 62 || !Hl || !Wl) return TC_EINVAL;
+  *Hl = H >> level;
+  *Wl = W >> level;
+  return TC_OK;
+}
+
+extern "C" int tc_image_pyramid(const tc_tensor* frame, int32_t levels, const tc_tensor* out, void* stream) {
+  int st;
+  if ((st = check_tensor(frame, true)) != TC_OK) return st;
+  if (frame->ndim != 2) return TC_ESHAPE;
+  if (frame->dtype != TC_U8 && frame->dtype != TC_F16 && frame->dtype != TC_F32) return TC_EDTYPE;
+  if (levels < 1 || levels > 16) return TC_EINVAL;
+  const int64_t H = frame->shape[0], W = frame->shape[1];
+  if ((H >> (levels - 1)) < 1 || (W >> (levels - 1)) < 1) return TC_ESHAPE;
+  if (H > (1LL << 24) || W > (1LL << 24)) return TC_ESHAPE;
+  if (levels > 1 && !out) return TC_EINVAL;
+  for (int l = 1; l < levels; ++l) {
+    const tc_tensor* o = &out[l - 1];
+    if ((st = check_tensor(o, true)) != TC_OK) return st;
+    if (o->ndim != 2 || o->dtype != TC_F32) return o->dtype != TC_F32 ? TC_EDTYPE : TC_ESHAPE;
+    if (o->shape[0] != (H >> l) || o->shape[1] != (W >> l)) return TC_ESHAPE;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  Image2D src{frame->data, frame->dtype, frame->stride[0], frame->stride[1]};
+  for (int l = 1; l < levels; ++l) {
+    const tc_tensor* o = &out[l - 1];
+    hipError_t e = launch_pyramid_level(src, reinterpret_cast<float*>(o->data), o->stride[0], o->stride[1],
+                                        (int)o->shape[0], (int)o->shape[1], s);
+    if (e != hipSuccess) return TC_EDEVICE;
+    src = Image2D{o->data, TC_F32, o->stride[0], o->stride[1]};
+  }
+  return TC_OK;
+}
+
+extern "C" int tc_horn_derivs(const tc_tensor* prev, const tc_tensor* next, const tc_tensor* ex, const tc_tensor* ey,
+                              const tc_tensor* et, void* stream) {
+  int st;
+  const tc_tensor* ins[2] = {prev, next};
+  const tc_tensor* outs[3] = {ex, ey, et};
+  for (auto t : ins) {
+    if ((st = check_tensor(t, true)) != TC_OK) return st;
+    if (t->ndim != 2) return TC_ESHAPE;
+  }
+  if (prev->dtype != next->dtype) return TC_EDTYPE;
+  if (prev->dtype != TC_U8 && prev->dtype != TC_F16 && prev->dtype != TC_F32) return TC_EDTYPE;
+  if (prev->shape[0] != next->shape[0] || prev->shape[1] != next->shape[1]) return TC_ESHAPE;
+  const int64_t H = prev->shape[0], W = prev->shape[1];
+  if (H < 2 || W < 2 || H > (1LL << 24) || W > (1LL << 24)) return TC_ESHAPE;
+  const int odt = ex ? ex->dtype : -1;
+  for (auto t : outs) {
+    if ((st = check_tensor(t, true)) != TC_OK) return st;
+    if (t->ndim != 2) return TC_ESHAPE;
+    if (t->dtype != odt) return TC_EDTYPE;
+    if (t->shape[0] != H - 1 || t->shape[1] != W - 1) return TC_ESHAPE;
+  }
+  if (odt != TC_F32 && odt != TC_I32) return TC_EDTYPE;
+  if (odt == TC_I32 && prev->dtype != TC_U8) return TC_EDTYPE;
+  const int64_t os0[3] = {ex->stride[0], ey->stride[0], et->stride[0]};
+  const int64_t os1[3] = {ex->stride[1], ey->stride[1], et->stride[1]};
+  Image2D a{prev->data, prev->dtype, prev->stride[0], prev->stride[1]};
+  Image2D b{next->data, next->dtype, next->stride[0], next->stride[1]};
+  return hip_status(launch_horn(a, b, (int)H, (int)W, ex->data, ey->data, et->data, odt, os0, os1,
+                                reinterpret_cast<hipStream_t>(stream)));
+}
+
+// ============================================================================ time to contact
+struct tc_ttc_plan {
+  int dtype = 0;
+  int levels = 0;
+  int band_rows = 0;
+  int n_seqs = 0;
+  int64_t n_items = 0;
+  int64_t n_pairs = 0;
+  int64_t n_partial_floats = 0;
+  size_t table_bytes = 0;
+  size_t ws_bytes = 0;
+  int grid = 0;
+  SeqDesc* table = nullptr;  // pinned host copy
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Band height per (dtype, levels): the rows a wave owns.  Chosen by the tuning
+// sweep of the fused pass; a multiple of 2^(levels-1) for every entry.
+int choose_band_rows(int dtype, int levels) {
+  (void)levels;
+  return dtype == TC_U8 ? 16 : 8;
+}
+
+int validate_seq(const tc_seq& q, int dtype, int levels) {
+  const int es = elem_size(dtype);
+  if (!q.frame0) return TC_EINVAL;
+  if (q.levels != levels) return TC_EINVAL;
+  if (q.n_frames < 2) return TC_EINVAL;
+  if (q.H < 2 || q.W < 2 || q.H > (1 << 20) || q.W > (1 << 20)) return TC_ESHAPE;
+  if ((q.H >> (levels - 1)) < 2 || (q.W >> (levels - 1)) < 2) return TC_ESHAPE;
+  if (q.row_stride < q.W) return TC_ESHAPE;
+  if (reinterpret_cast<uintptr_t>(q.frame0) % (uintptr_t)es) return TC_EINVAL;
+  return TC_OK;
+}
+
+// 8-pixel lane chunks start at multiples of 8 pixels; they can be fetched with
+// one 8-byte (u8) or 16-byte (f16) load when frames and rows keep that alignment.
+int vector_ok(const tc_seq& q, int dtype) {
+  const int es = elem_size(dtype);
+  const int64_t align = 8 * es;
+  return (reinterpret_cast<uintptr_t>(q.frame0) % (uintptr_t)align) == 0 && (q.row_stride * es) % align == 0 &&
+         (q.frame_stride * es) % align == 0;
+}
+
+void fill_desc(SeqDesc& d, const tc_seq& q, int dtype, int band_rows) {
+  d.frame0 = q.frame0;
+  d.frame_stride = q.frame_stride;
+  d.row_stride = q.row_stride;
+  d.H = q.H;
+  d.W = q.W;
+  d.n_frames = q.n_frames;
+  d.levels = q.levels;
+  d.band_rows = band_rows;
+  d.n_bands = (q.H + band_rows - 1) / band_rows;
+  d.n_bgroups = (d.n_bands + kWavesPerItem - 1) / kWavesPerItem;
+  const int n_seg = (q.W - 1 + kSegCols - 1) / kSegCols;
+  d.n_cw = (n_seg + 3) / 4;
+  d.n_witems = d.n_bgroups * d.n_cw * kWavesPerItem;
+  d.vec = vector_ok(q, dtype);
+}
+
+int persistent_grid(int64_t n_items) {
+  const int n_cu = current_cu_count();
+  int64_t g = std::min<int64_t>(n_items, (int64_t)n_cu * 8);
+  if (g >= 8) g -= g % 8;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+}  // namespace
+
+extern "C" int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan) {
+  if (!plan) return TC_EINVAL;
+  *plan = nullptr;
+  if (!seqs || n_seqs < 1 || n_seqs > (1 << 20)) return TC_EINVAL;
+  if (dtype != TC_U8 && dtype != TC_F16) return TC_EDTYPE;
+  const int levels = seqs[0].levels;
+  if (levels < 1 || levels > TC_MAX_LEVELS) return TC_EINVAL;
+  for (int i = 0; i < n_seqs; ++i) {
+    const int st = validate_seq(seqs[i], dtype, levels);
+    if (st != TC_OK) return st;
+  }
+  const int rh = choose_band_rows(dtype, levels);
+  if (!fused_variant_exists(dtype, levels, rh)) return TC_EINVAL;
+
+  tc_ttc_plan* p = new (std::nothrow) tc_ttc_plan();
+  if (!p) return TC_ENOMEM;
+  p->dtype = dtype;
+  p->levels = levels;
+  p->band_rows = rh;
+  p->n_seqs = n_seqs;
+  p->table_bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
+  if (hipHostMalloc(reinterpret_cast<void**>(&p->table), p->table_bytes, hipHostMallocDefault) != hipSuccess) {
+    delete p;
+    return TC_EDEVICE;
+  }
+  memset(p->table, 0, p->table_bytes);
+  int64_t items = 0, pairs = 0, floats = 0;
+  for (int i = 0; i < n_seqs; ++i) {
+    SeqDesc& d = p->table[i];
+    fill_desc(d, seqs[i], dtype, rh);
+    d.item_begin = items;
+    d.pair_begin = pairs;
+    d.partial_begin = floats;
+    items += (int64_t)d.n_bgroups * d.n_cw;
+    pairs += d.n_frames - 1;
+    floats += (int64_t)(d.n_frames - 1) * levels * d.n_witems * 10;
+  }
+  p->n_items = items;
+  p->n_pairs = pairs;
+  p->n_partial_floats = floats;
+  p->ws_bytes = p->table_bytes + align_up((size_t)floats * sizeof(float));
+  p->grid = persistent_grid(items);
+  *plan = p;
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_plan_info(const tc_ttc_plan* plan, size_t* ws_bytes, int64_t* n_pairs,
+                                int64_t* n_level_records) {
+  if (!plan) return TC_EINVAL;
+  if (ws_bytes) *ws_bytes = plan->ws_bytes;
+  if (n_pairs) *n_pairs = plan->n_pairs;
+  if (n_level_records) *n_level_records = plan->n_pairs * plan->levels;
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_plan_upload(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  if (!plan || !ws) return TC_EINVAL;
+  if (ws_bytes < plan->ws_bytes) return TC_ENOMEM;
+  return hip_status(hipMemcpyAsync(ws, plan->table, sizeof(SeqDesc) * (size_t)plan->n_seqs, hipMemcpyHostToDevice,
+                                   reinterpret_cast<hipStream_t>(stream)));
+}
+
+extern "C" int tc_ttc_plan_run_phase(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, tc_ttc_level* levels_out,
+                                     tc_ttc_pick* picks_out, int32_t phase, void* stream) {
+  if (!plan || !ws || phase < 1 || phase > 3) return TC_EINVAL;
+  if ((phase & TC_PHASE_FINISH) && (!levels_out || !picks_out)) return TC_EINVAL;
+  if (ws_bytes < plan->ws_bytes) return TC_ENOMEM;
+  FusedLaunch f{};
+  f.dt = plan->dtype;
+  f.levels = plan->levels;
+  f.band_rows = plan->band_rows;
+  f.table = reinterpret_cast<const SeqDesc*>(ws);
+  f.n_seqs = plan->n_seqs;
+  f.n_items = plan->n_items;
+  f.n_pairs = plan->n_pairs;
+  f.partials = reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + plan->table_bytes);
+  f.grid = plan->grid;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if ((phase & TC_PHASE_FUSED) && launch_ttc_fused(f, s) != hipSuccess) return TC_EDEVICE;
+  if ((phase & TC_PHASE_FINISH) && launch_ttc_finish(f, levels_out, picks_out, s) != hipSuccess) return TC_EDEVICE;
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_plan_run(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, tc_ttc_level* levels_out,
+                               tc_ttc_pick* picks_out, void* stream) {
+  return tc_ttc_plan_run_phase(plan, ws, ws_bytes, levels_out, picks_out, TC_PHASE_FUSED | TC_PHASE_FINISH, stream);
+}
+
+extern "C" void tc_ttc_plan_destroy(tc_ttc_plan* plan) {
+  if (!plan) return;
+  if (plan->table) {
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(plan->table);
+  }
+  delete plan;
+}
+
+extern "C" int tc_ttc_solve_batched(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, void* ws, size_t ws_bytes,
+                                    tc_ttc_level* levels_out, tc_ttc_pick* picks_out, void* stream) {
+  tc_ttc_plan* p = nullptr;
+  int st = tc_ttc_plan_create(seqs, n_seqs, dtype, &p);
+  if (st != TC_OK) return st;
+  st = tc_ttc_plan_upload(p, ws, ws_bytes, stream);
+  if (st == TC_OK) st = tc_ttc_plan_run(p, ws, ws_bytes, levels_out, picks_out, stream);
+  if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess && st == TC_OK) st = TC_EDEVICE;
+  tc_ttc_plan_destroy(p);
+  return st;
+}
+
+namespace {
+
+int pair_desc(const tc_tensor* prev, const tc_tensor* next, int32_t levels, SeqDesc& d) {
+  int st;
+  if ((st = check_tensor(prev, true)) != TC_OK) return st;
+  if ((st = check_tensor(next, true)) != TC_OK) return st;
+  if (prev->ndim != 2 || next->ndim != 2) return TC_ESHAPE;
+  if (prev->dtype != next->dtype) return TC_EDTYPE;
+  if (prev->dtype != TC_U8 && prev->dtype != TC_F16) return TC_EDTYPE;
+  if (prev->shape[0] != next->shape[0] || prev->shape[1] != next->shape[1]) return TC_ESHAPE;
+  if (prev->stride[1] != 1 || next->stride[1] != 1 || prev->stride[0] != next->stride[0]) return TC_ESHAPE;
+  if (levels < 1 || levels > TC_MAX_LEVELS) return TC_EINVAL;
+  if (prev->shape[0] > (1 << 20) || prev->shape[1] > (1 << 20)) return TC_ESHAPE;
+  const int es = elem_size(prev->dtype);
+  const int64_t diff = reinterpret_cast<const char*>(next->data) - reinterpret_cast<const char*>(prev->data);
+  if (diff % es) return TC_EINVAL;
+  tc_seq q;
+  q.frame0 = prev->data;
+  q.frame_stride = diff / es;
+  q.row_stride = prev->stride[0];
+  q.H = (int32_t)prev->shape[0];
+  q.W = (int32_t)prev->shape[1];
+  q.n_frames = 2;
+  q.levels = levels;
+  if ((st = validate_seq(q, prev->dtype, levels)) != TC_OK) return st;
+  fill_desc(d, q, prev->dtype, choose_band_rows(prev->dtype, levels));
+  d.item_begin = 0;
+  d.pair_begin = 0;
+  d.partial_begin = 0;
+  return TC_OK;
+}
+
+size_t pair_ws_bytes(const SeqDesc& d) { return align_up((size_t)d.levels * d.n_witems * 10 * sizeof(float)); }
+
+}  // namespace
+
+extern "C" int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_t* ws_bytes) {
+  if (!ws_bytes || H < 2 || W < 2 || H > (1 << 20) || W > (1 << 20) || levels < 1 || levels > TC_MAX_LEVELS)
+    return TC_EINVAL;
+  size_t best = 0;
+  const int dts[2] = {TC_U8, TC_F16};
+  for (int dt : dts) {
+    tc_seq q{};
+    q.H = (int32_t)H;
+    q.W = (int32_t)W;
+    q.n_frames = 2;
+    q.levels = levels;
+    SeqDesc d{};
+    fill_desc(d, q, dt, choose_band_rows(dt, levels));
+    best = std::max(best, pair_ws_bytes(d));
+  }
+  *ws_bytes = best;
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_t levels, void* ws, size_t ws_bytes,
+                            tc_ttc_level* levels_out, tc_ttc_pick* pick_out, void* stream) {
+  if (!ws || !levels_out || !pick_out) return TC_EINVAL;
+  SeqDesc d{};
+  int st = pair_desc(prev, next, levels, d);
+  if (st != TC_OK) return st;
+  if (ws_bytes < pair_ws_bytes(d)) return TC_ENOMEM;
+  FusedLaunch f{};
+  f.dt = prev->dtype;
+  f.levels = levels;
+  f.band_rows = d.band_rows;
+  f.table = nullptr;
+  f.n_seqs = 1;
+  f.inl = d;
+  f.n_items = (int64_t)d.n_bgroups * d.n_cw;
+  f.n_pairs = 1;
+  f.partials = reinterpret_cast<float*>(ws);
+  f.grid = persistent_grid(f.n_items);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (launch_ttc_fused(f, s) != hipSuccess) return TC_EDEVICE;
+  if (launch_ttc_finish(f, levels_out, pick_out, s) != hipSuccess) return TC_EDEVICE;
+  return TC_OK;
+}

@@ -1,0 +1,180 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, its struct layouts match the binding, and argument
+validation rejects bad input before anything is launched (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1612_08825_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ttcconv.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libttcconv.so is not built (python -m paper_1612_08825_amd.build)")
+    return L.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(tc_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_function(lib):
+    names = header_functions()
+    assert len(names) >= 16
+    assert set(names) == set(L.SIGNATURES), "binding signatures and header disagree"
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (tc_[a-z0-9_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header():
+    src = r"""
+    #include <stdio.h>
+    #include <stddef.h>
+    #include "ttcconv.h"
+    int main(void) {
+      printf("%zu %zu %zu %zu\n", sizeof(tc_tensor), sizeof(tc_seq), sizeof(tc_ttc_level), sizeof(tc_ttc_pick));
+      printf("%zu %zu %zu %zu\n", offsetof(tc_ttc_level, A), offsetof(tc_ttc_level, n), offsetof(tc_ttc_level, status),
+             offsetof(tc_ttc_pick, level));
+      printf("%zu %zu\n", offsetof(tc_tensor, shape), offsetof(tc_seq, H));
+      return 0;
+    }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == C.sizeof(L.TcTensor)
+    assert vals[1] == C.sizeof(L.TcSeq)
+    assert vals[2] == L.LEVEL_DTYPE.itemsize
+    assert vals[3] == L.PICK_DTYPE.itemsize
+    assert vals[4] == L.LEVEL_DTYPE.fields["A"][1]
+    assert vals[5] == L.LEVEL_DTYPE.fields["n"][1]
+    assert vals[6] == L.LEVEL_DTYPE.fields["status"][1]
+    assert vals[7] == L.PICK_DTYPE.fields["level"][1]
+    assert vals[8] == L.TcTensor.shape.offset
+    assert vals[9] == L.TcSeq.H.offset
+
+
+def test_status_strings(lib):
+    for code in (0, 1, 2, 3, -1, -2, -3, -4, -5, -6, 99):
+        assert lib.tc_status_str(code)
+    assert lib.tc_version() == 100
+
+
+def _desc(shape, dt, data=None):
+    d = L.TcTensor()
+    d.data = data
+    d.dtype = dt
+    d.ndim = len(shape)
+    s = 1
+    for i in range(len(shape) - 1, -1, -1):
+        d.shape[i] = shape[i]
+        d.stride[i] = s
+        s *= shape[i]
+    return d
+
+
+def test_conv_out_shape_queries(lib):
+    out = (C.c_int64 * 8)()
+    x, k = _desc((10, 7), L.TC_F32), _desc((3, 4), L.TC_F32)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(k), L.TC_FULL, out) == 0
+    assert (out[0], out[1]) == (12, 10)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(k), L.TC_SAME, out) == 0
+    assert (out[0], out[1]) == (10, 7)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(k), L.TC_VALID, out) == 0
+    assert (out[0], out[1]) == (8, 4)
+    big = _desc((12, 9), L.TC_F32)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(big), L.TC_VALID, out) == 0
+    assert (out[0], out[1]) == (3, 3)
+    mixed = _desc((12, 3), L.TC_F32)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(mixed), L.TC_VALID, out) == L.TC_ESHAPE
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(k), 7, out) == L.TC_EINVAL
+    kr = _desc((3,), L.TC_F32)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(kr), L.TC_FULL, out) == L.TC_ESHAPE
+    ki = _desc((3, 4), L.TC_I32)
+    assert lib.tc_conv_out_shape(C.byref(x), C.byref(ki), L.TC_FULL, out) == L.TC_EDTYPE
+    xu = _desc((10, 7), L.TC_U8)
+    assert lib.tc_conv_out_shape(C.byref(xu), C.byref(ki), L.TC_FULL, out) == 0
+    assert lib.tc_conv_out_shape(C.byref(xu), C.byref(k), L.TC_FULL, out) == L.TC_EDTYPE
+
+
+def test_conv_nd_rejects_before_launch(lib):
+    x = _desc((10, 7), L.TC_F32, data=16)
+    k = _desc((3, 3), L.TC_F32, data=16)
+    y_bad = _desc((11, 9), L.TC_F32, data=16)
+    assert lib.tc_conv_nd(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y_bad), None) == L.TC_ESHAPE
+    y_dt = _desc((12, 9), L.TC_I32, data=16)
+    assert lib.tc_conv_nd(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y_dt), None) == L.TC_EDTYPE
+    x_null = _desc((10, 7), L.TC_F32, data=None)
+    y = _desc((12, 9), L.TC_F32, data=16)
+    assert lib.tc_conv_nd(C.byref(x_null), C.byref(k), L.TC_FULL, C.byref(y), None) == L.TC_EINVAL
+    k_strided = _desc((3, 3), L.TC_F32, data=16)
+    k_strided.stride[1] = 2
+    assert lib.tc_conv_nd(C.byref(x), C.byref(k_strided), L.TC_FULL, C.byref(y), None) == L.TC_ESHAPE
+    x0 = _desc((10, 7), L.TC_F32, data=16)
+    x0.stride[0] = 0
+    assert lib.tc_conv_nd(C.byref(x0), C.byref(k), L.TC_FULL, C.byref(y), None) == L.TC_ESHAPE
+
+
+def test_pyramid_and_horn_validation(lib):
+    Hl, Wl = C.c_int64(), C.c_int64()
+    assert lib.tc_pyramid_shape(481, 641, 3, C.byref(Hl), C.byref(Wl)) == 0
+    assert (Hl.value, Wl.value) == (60, 80)
+    f = _desc((16, 16), L.TC_U8, data=16)
+    assert lib.tc_image_pyramid(C.byref(f), 0, None, None) == L.TC_EINVAL
+    assert lib.tc_image_pyramid(C.byref(f), 6, None, None) == L.TC_ESHAPE  # 16 >> 5 == 0
+    outs = (L.TcTensor * 1)(_desc((8, 8), L.TC_F16, data=16))
+    assert lib.tc_image_pyramid(C.byref(f), 2, outs, None) == L.TC_EDTYPE
+    outs = (L.TcTensor * 1)(_desc((8, 7), L.TC_F32, data=16))
+    assert lib.tc_image_pyramid(C.byref(f), 2, outs, None) == L.TC_ESHAPE
+    g = _desc((16, 16), L.TC_F16, data=16)
+    e = _desc((15, 15), L.TC_F32, data=16)
+    assert lib.tc_horn_derivs(C.byref(f), C.byref(g), C.byref(e), C.byref(e), C.byref(e), None) == L.TC_EDTYPE
+    ei = _desc((15, 15), L.TC_I32, data=16)
+    assert lib.tc_horn_derivs(C.byref(g), C.byref(g), C.byref(ei), C.byref(ei), C.byref(ei), None) == L.TC_EDTYPE
+    e_bad = _desc((15, 16), L.TC_F32, data=16)
+    assert lib.tc_horn_derivs(C.byref(f), C.byref(f), C.byref(e_bad), C.byref(e), C.byref(e), None) == L.TC_ESHAPE
+
+
+def _seq(H, W, F=2, levels=1, ptr=4096, row_stride=None):
+    q = L.TcSeq()
+    q.frame0 = ptr
+    q.frame_stride = H * (row_stride or W)
+    q.row_stride = row_stride or W
+    q.H, q.W, q.n_frames, q.levels = H, W, F, levels
+    return q
+
+
+def test_ttc_plan_validation(lib):
+    h = C.c_void_p()
+    bad = [
+        (_seq(64, 64, levels=5), L.TC_U8, L.TC_EINVAL),
+        (_seq(64, 64, F=1), L.TC_U8, L.TC_EINVAL),
+        (_seq(12, 64, levels=4), L.TC_U8, L.TC_ESHAPE),  # level 3 would be 1 row
+        (_seq(64, 64), L.TC_F32, L.TC_EDTYPE),
+        (_seq(64, 64, ptr=4097), L.TC_F16, L.TC_EINVAL),  # frame not aligned to its element size
+        (_seq(64, 64, row_stride=32), L.TC_U8, L.TC_ESHAPE),
+    ]
+    for q, dt, code in bad:
+        arr = (L.TcSeq * 1)(q)
+        assert lib.tc_ttc_plan_create(arr, 1, dt, C.byref(h)) == code
+    mixed = (L.TcSeq * 2)(_seq(64, 64, levels=2), _seq(64, 64, levels=3))
+    assert lib.tc_ttc_plan_create(mixed, 2, L.TC_U8, C.byref(h)) == L.TC_EINVAL
+    n = C.c_size_t()
+    assert lib.tc_ttc_workspace_size(480, 640, 4, C.byref(n)) == 0 and n.value > 0
+    assert lib.tc_ttc_workspace_size(480, 640, 5, C.byref(n)) == L.TC_EINVAL

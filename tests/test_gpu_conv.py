@@ -1,0 +1,177 @@
+"""GPU parity of tc_conv_nd against the FP64 / exact-integer oracle.
+
+Integer convolutions must match exactly; float ones within
+|y - y64| <= 1e-5 * (|x| (*) |k|) element-wise and 1e-5 norm-wise.  Shapes span
+several 64x64 output tiles with ragged tails, kernels larger than the image,
+strided views, every mode, ranks 1-4, and the full benchmark sizes (checked on
+sampled outputs the oracle computes one at a time)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1612_08825_amd import synth
+from tolerance import TAU_CONV, conv_bound
+
+pytestmark = pytest.mark.gpu
+
+MAXERR = {}
+
+
+@pytest.fixture(scope="module")
+def api(gpu_lib):
+    from paper_1612_08825_amd import api
+
+    return api
+
+
+def _check_float(y, x, k, mode, tag):
+    ref = O.conv(x, k, mode)
+    bound = conv_bound(x, k, mode)
+    err = np.abs(y.astype(np.float64) - ref)
+    rel = float((err / np.maximum(bound / TAU_CONV, 1e-300)).max()) if err.size else 0.0
+    MAXERR[tag] = rel
+    print(f"[conv {tag}] max |err| / sum|x||k| = {rel:.3e}", flush=True)
+    assert np.all(err <= bound + 1e-30)
+    if ref.size:
+        assert err.max() <= TAU_CONV * max(np.abs(ref).max(), 1e-30)
+
+
+SHAPES_2D = [((70, 130), (3, 3)), ((129, 65), (7, 7)), ((100, 77), (15, 15)), ((5, 6), (9, 11)),
+             ((64, 64), (1, 1)), ((1, 200), (1, 5)), ((67, 67), (2, 5)), ((40, 33), (16, 16)), ((33, 19), (20, 3))]
+
+
+@pytest.mark.parametrize("xs,ks", SHAPES_2D)
+@pytest.mark.parametrize("mode", ["full", "same", "valid"])
+def test_conv2d_f32(api, xs, ks, mode):
+    try:
+        O.conv_out_shape(xs, ks, mode)
+    except ValueError:
+        pytest.skip("mixed extents are rejected in valid mode")
+    x = synth.conv_image(xs, case=1)
+    k = synth.conv_kernel(ks, case=1)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+    _check_float(y, x, k, mode, f"f32 {xs}*{ks} {mode}")
+
+
+@pytest.mark.parametrize("xs,ks", SHAPES_2D[:5])
+@pytest.mark.parametrize("mode", ["full", "valid"])
+def test_conv2d_u8_exact(api, xs, ks, mode):
+    try:
+        O.conv_out_shape(xs, ks, mode)
+    except ValueError:
+        pytest.skip("mixed extents are rejected in valid mode")
+    x = synth.conv_image(xs, case=2, dtype="u8")
+    k = synth.conv_kernel(ks, case=2, dtype="i32")
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+    assert y.dtype == np.int32
+    np.testing.assert_array_equal(y.astype(np.int64), O.conv(x, k, mode))
+
+
+def test_conv2d_f16_input(api):
+    x = synth.conv_image((90, 75), case=3, dtype="f16")
+    k = synth.conv_kernel((5, 5), case=3)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), "same").cpu().numpy()
+    _check_float(y, x, k, "same", "f16 90x75*5x5")
+
+
+def test_conv_strided_views(api):
+    base = synth.conv_image((150, 140), case=4)
+    xg = torch.from_numpy(base).cuda()[3::2, 5:128]  # row stride 280, column slice
+    x = base[3::2, 5:128]
+    k = synth.conv_kernel((3, 4), case=4)
+    kg = torch.from_numpy(k).cuda()
+    big = torch.full((200, 200), -7.0, device="cuda")
+    out = big[10:10 + x.shape[0] + 2, 20:20 + x.shape[1] + 3]
+    api.conv_nd(xg, kg, "full", out=out)
+    _check_float(out.cpu().numpy(), x, k, "full", "strided")
+    assert float(big[0, 0]) == -7.0 and float(big[199, 199]) == -7.0  # nothing written outside the view
+
+
+@pytest.mark.parametrize("xs,ks", [((9, 70, 66), (3, 3, 3)), ((3, 5, 4), (4, 6, 5)), ((6, 31, 29), (2, 7, 1))])
+@pytest.mark.parametrize("mode", ["full", "same", "valid"])
+def test_conv3d(api, xs, ks, mode):
+    try:
+        O.conv_out_shape(xs, ks, mode)
+    except ValueError:
+        pytest.skip("mixed extents are rejected in valid mode")
+    x = synth.conv_image(xs, case=5)
+    k = synth.conv_kernel(ks, case=5)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+    _check_float(y, x, k, mode, f"3d {xs}*{ks} {mode}")
+    xu = synth.conv_image(xs, case=5, dtype="u8")
+    ku = synth.conv_kernel(ks, case=5, dtype="i32")
+    yu = api.conv_nd(torch.from_numpy(xu).cuda(), torch.from_numpy(ku).cuda(), mode).cpu().numpy()
+    np.testing.assert_array_equal(yu.astype(np.int64), O.conv(xu, ku, mode))
+
+
+@pytest.mark.parametrize("xs,ks", [((1000,), (7,)), ((5,), (9,)), ((4, 5, 6, 7), (2, 3, 2, 3)), ((3, 2, 2, 2, 3), (2, 2, 1, 2, 2))])
+def test_conv_other_ranks(api, xs, ks):
+    for mode in ("full", "same"):
+        x = synth.conv_image(xs, case=6)
+        k = synth.conv_kernel(ks, case=6)
+        y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+        _check_float(y, x, k, mode, f"rank{len(xs)} {xs} {mode}")
+        xu = synth.conv_image(xs, case=6, dtype="u8")
+        ku = synth.conv_kernel(ks, case=6, dtype="i32")
+        yu = api.conv_nd(torch.from_numpy(xu).cuda(), torch.from_numpy(ku).cuda(), mode).cpu().numpy()
+        np.testing.assert_array_equal(yu.astype(np.int64), O.conv(xu, ku, mode))
+
+
+def test_conv_int_bounds(api):
+    from paper_1612_08825_amd import _lib as L
+
+    x = torch.from_numpy(synth.conv_image((20, 20), dtype="u8")).cuda()
+    k = torch.zeros((3, 3), dtype=torch.int32)
+    k[1, 1] = 8421504  # 255 * 8421504 = 2147483520 <= 2^31 - 1, beyond the 24-bit multiply
+    y = api.conv_nd(x, k.cuda(), "same").cpu().numpy()
+    np.testing.assert_array_equal(y.astype(np.int64), O.conv(x.cpu().numpy(), k.numpy(), "same"))
+    k[0, 0] = 1
+    with pytest.raises(L.TTCError) as e:
+        api.conv_nd(x, k.cuda(), "same")
+    assert e.value.code == L.TC_EOVERFLOW
+
+
+def _sample_index(shape, n, rng):
+    idx = [tuple(int(rng.integers(e)) for e in shape) for _ in range(n)]
+    corners = [tuple(c) for c in np.ndindex(*(2,) * len(shape))]
+    idx += [tuple(0 if b == 0 else e - 1 for b, e in zip(c, shape)) for c in corners]
+    idx += [tuple(min(7, e - 1) if d == 0 else e // 2 for d, e in enumerate(shape))]
+    return idx
+
+
+@pytest.mark.parametrize("N", [1024, 2048, 4096])
+@pytest.mark.parametrize("K", [3, 7, 15])
+def test_conv_benchmark_sizes_sampled(api, N, K):
+    x = synth.conv_image((N, N), case=100 + N)
+    k = synth.conv_kernel((K, K), case=100 + K)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), "full")
+    assert tuple(y.shape) == (N + K - 1, N + K - 1)
+    rng = np.random.default_rng(N * K)
+    idx = _sample_index(tuple(y.shape), 400, rng)
+    got = y.cpu().numpy()[tuple(np.array(idx).T)]
+    ref = O.conv_at(x, k, "full", idx)
+    bound = TAU_CONV * O.conv_at(np.abs(x.astype(np.float64)), np.abs(k.astype(np.float64)), "full", idx)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_conv3d_benchmark_size_sampled(api):
+    x = synth.conv_image((64, 256, 256), case=300)
+    k = synth.conv_kernel((3, 3, 3), case=300)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), "full")
+    assert tuple(y.shape) == (66, 258, 258)
+    rng = np.random.default_rng(3)
+    idx = _sample_index(tuple(y.shape), 400, rng)
+    got = y.cpu().numpy()[tuple(np.array(idx).T)]
+    ref = O.conv_at(x, k, "full", idx)
+    bound = TAU_CONV * O.conv_at(np.abs(x.astype(np.float64)), np.abs(k.astype(np.float64)), "full", idx)
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+def test_conv_u8_benchmark_size_sampled(api):
+    x = synth.conv_image((2048, 2048), case=400, dtype="u8")
+    k = synth.conv_kernel((7, 7), case=400, dtype="i32")
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), "full").cpu().numpy()
+    rng = np.random.default_rng(4)
+    idx = _sample_index(y.shape, 1000, rng)
+    np.testing.assert_array_equal(y[tuple(np.array(idx).T)].astype(np.int64), O.conv_at(x, k, "full", idx))

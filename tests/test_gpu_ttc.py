@@ -1,0 +1,192 @@
+"""GPU parity of the fused time-to-contact path (tc_ttc_solve, the batched
+plan) against the FP64 oracle.
+
+Per level: every sum within TAU_SUM * sum|terms| of the oracle's; A, B, C,
+TTC, FOE within the first-order propagation of those bounds through the 3x3
+solve (tests/tolerance.py); statuses equal; the multi-scale choice equal
+wherever neighbouring levels are not within tolerance of a tie."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1612_08825_amd import synth
+from tolerance import TAU_SUM, abs_sums, solution_bounds
+
+pytestmark = pytest.mark.gpu
+
+WORST = {"sum": 0.0, "C": 0.0, "foe": 0.0}
+
+
+@pytest.fixture(scope="module")
+def api(gpu_lib):
+    from paper_1612_08825_amd import api
+
+    return api
+
+
+def _frames_np(frames):
+    return frames.cpu().numpy() if isinstance(frames, torch.Tensor) else np.asarray(frames)
+
+
+def check_pair(rec, pick, P0, P1, levels, tag=""):
+    """Compare one pair's GPU level records and pick with the oracle."""
+    H0, W0 = P0.shape
+    ref = O.ttc_pair(P0, P1, levels)
+    p0 = O.pyramid(P0, levels)
+    p1 = O.pyramid(P1, levels)
+    for l in range(levels):
+        r, g = ref[l], rec[l]
+        assert g["level"] == l
+        assert g["n"] == r["n"]
+        assert g["status"] == r["status"], (tag, l, g["status"], r["status"])
+        a = abs_sums(p0[l], p1[l], l, H0, W0)
+        err = np.abs(g["sums"] - r["sums"])
+        rel = float(np.max(err / np.maximum(a, 1e-300)))
+        WORST["sum"] = max(WORST["sum"], rel)
+        assert np.all(err <= TAU_SUM * a + 1e-300), (tag, l, rel)
+        if r["status"] != O.STATUS_OK:
+            assert math.isnan(g["ttc"])
+            continue
+        b = solution_bounds(r["sums"], a)
+        for key in ("A", "B", "C", "ttc", "x0", "y0"):
+            assert abs(g[key] - r[key]) <= b[key], (tag, l, key, g[key], r[key], b[key])
+        WORST["C"] = max(WORST["C"], abs(g["C"] - r["C"]) / abs(r["C"]))
+        WORST["foe"] = max(WORST["foe"], abs(g["x0"] - r["x0"]), abs(g["y0"] - r["y0"]))
+        assert abs(g["resid"] - r["resid"]) <= 1e-3 * abs(r["resid"]) + 1e-6 * a[9]
+    sel = O.select_level(ref)
+    ttcs = [r["ttc"] for r in ref]
+    near_tie = any(abs(ttcs[i + 1] - ttcs[i]) <= solution_bounds(ref[i]["sums"], abs_sums(p0[i], p1[i], i, H0, W0))["ttc"]
+                   + solution_bounds(ref[i + 1]["sums"], abs_sums(p0[i + 1], p1[i + 1], i + 1, H0, W0))["ttc"]
+                   for i in range(levels - 1) if ref[i]["status"] == 0 and ref[i + 1]["status"] == 0)
+    if not near_tie:
+        assert pick["level"] == sel, (tag, pick["level"], sel, ttcs)
+        assert pick["ttc"] == rec[sel]["ttc"]
+
+
+def test_plain_video_single_pairs(api):
+    """The 8-frame 128x128 u8 video, one tc_ttc_solve call per pair, 1 level."""
+    v = synth.plain_ttc_video()
+    fr = torch.from_numpy(v.frames).cuda()
+    for t in range(v.n_frames - 1):
+        lv, pk = api.ttc_solve(fr[t], fr[t + 1], 1)
+        rec = api.decode_levels(lv)
+        pick = api.decode_picks(pk)[0]
+        check_pair(rec, pick, v.frames[t], v.frames[t + 1], 1, f"pair{t}")
+        assert abs(rec[0]["ttc"] - 40.0) < 2.0  # the analytic ground truth is 40 frames
+    print(f"[ttc plain] worst sum err/sum|t| {WORST['sum']:.2e} rel C {WORST['C']:.2e} foe {WORST['foe']:.2e}")
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3, 4])
+def test_plain_video_batched_levels(api, levels):
+    v = synth.plain_ttc_video(F=8)
+    fr = torch.from_numpy(v.frames).cuda()
+    recs, picks = api.ttc_solve_batched([fr], levels)
+    assert recs.shape == (7 * levels,) and picks.shape == (7,)
+    for t in range(7):
+        check_pair(recs[t * levels:(t + 1) * levels], picks[t], v.frames[t], v.frames[t + 1], levels, f"t{t}")
+
+
+@pytest.mark.parametrize("H,W,levels,dtype", [(97, 131, 3, "u8"), (130, 250, 4, "f16"), (67, 700, 2, "u8"),
+                                              (200, 489, 4, "u8"), (16, 16, 4, "f16"), (171, 1000, 1, "f16"),
+                                              (9, 9, 1, "u8")])
+def test_ragged_sizes(api, H, W, levels, dtype):
+    v = synth.multiscale_video(H=H, W=W, F=3, foe=(W / 10, -H / 12), ttc_start=40, ttc_end=35, dtype=dtype)
+    fr = torch.from_numpy(v.frames).cuda()
+    recs, picks = api.ttc_solve_batched([fr], levels)
+    for t in range(2):
+        check_pair(recs[t * levels:(t + 1) * levels], picks[t], v.frames[t], v.frames[t + 1], levels, f"{H}x{W}")
+
+
+def test_batch_mix_equals_alone(api):
+    """Streams of uneven sizes in one plan: each pair equals the oracle, and the
+    records are bit-identical to running each stream alone."""
+    sizes = [(60, 80), (240, 320), (123, 517), (48, 1000), (480, 640)]
+    vids = []
+    for i, (H, W) in enumerate(sizes):
+        v = synth.multiscale_video(case=i, H=H, W=W, F=4, foe=(W / 9, H / 11), ttc_start=60, ttc_end=50)
+        vids.append(v)
+    gpu = [torch.from_numpy(v.frames).cuda() for v in vids]
+    recs, picks = api.ttc_solve_batched(gpu, 3)
+    off = 0
+    for v, g in zip(vids, gpu):
+        n = v.n_frames - 1
+        alone, alone_p = api.ttc_solve_batched([g], 3)
+        assert alone.tobytes() == recs[off * 3:(off + n) * 3].tobytes()
+        assert alone_p.tobytes() == picks[off:off + n].tobytes()
+        for t in range(n):
+            check_pair(recs[(off + t) * 3:(off + t + 1) * 3], picks[off + t], v.frames[t], v.frames[t + 1], 3)
+        off += n
+
+
+def test_pairs_as_two_frame_streams(api):
+    """Unrelated prev/next buffers described by frame_stride = next - prev."""
+    v = synth.multiscale_video(H=100, W=150, F=2, foe=(5, 5), ttc_start=50, ttc_end=49)
+    a = torch.from_numpy(v.frames[0]).cuda()
+    junk = torch.empty(12345, dtype=torch.uint8, device="cuda")
+    b = torch.from_numpy(v.frames[1]).cuda()
+    del junk
+    plan = api.TTCPlan([api.seq_from_pair(a, b, 2)], torch.uint8, keep=[a, b])
+    plan.run()
+    torch.cuda.synchronize()
+    recs, picks = plan.results()
+    plan.close()
+    check_pair(recs, picks[0], v.frames[0], v.frames[1], 2, "pair-stream")
+
+
+def test_symmetric_video(api):
+    v = synth.plain_ttc_video(H=64, W=80, F=2, symmetric=True)
+    fr = torch.from_numpy(v.frames).cuda()
+    recs, _ = api.ttc_solve_batched([fr], 3)
+    for l in range(3):
+        r = recs[l]
+        ref = O.ttc_pair(v.frames[0], v.frames[1], 3)[l]
+        assert ref["A"] == 0.0 and ref["B"] == 0.0
+        p0 = O.pyramid(v.frames[0], 3)[l]
+        p1 = O.pyramid(v.frames[1], 3)[l]
+        b = solution_bounds(ref["sums"], abs_sums(p0, p1, l, 64, 80))
+        assert abs(r["A"]) <= b["A"] and abs(r["B"]) <= b["B"]
+
+
+def test_ramp_is_singular_and_nan_is_nonfinite(api):
+    i, j = np.meshgrid(np.arange(32), np.arange(48), indexing="ij")
+    ramp = np.stack([(2 * j + i + 20 + 3 * t).astype(np.uint8) for t in range(2)])
+    recs, picks = api.ttc_solve_batched([torch.from_numpy(ramp).cuda()], 2)
+    assert all(r["status"] == O.STATUS_SINGULAR for r in recs)
+    assert math.isnan(picks[0]["ttc"])
+    v = synth.plain_ttc_video(H=32, W=32, F=2, dtype="f16")
+    f = v.frames.copy()
+    f[1, 5, 7] = np.float16(np.nan)
+    recs, picks = api.ttc_solve_batched([torch.from_numpy(f).cuda()], 1)
+    assert recs[0]["status"] == O.STATUS_NONFINITE
+
+
+def test_multiscale_video_sampled(api):
+    """The 300-frame 640x480 u8 multi-scale video (4 levels): every pair on the
+    GPU in one pass, a sample of pairs against the oracle."""
+    v = synth.multiscale_video(device="cuda")
+    fr = v.frames
+    recs, picks = api.ttc_solve_batched([fr], 4)
+    assert recs.shape == (299 * 4,)
+    host = fr.cpu().numpy()
+    for t in (0, 57, 150, 298):
+        check_pair(recs[t * 4:(t + 1) * 4], picks[t], host[t], host[t + 1], 4, f"ms{t}")
+    print(f"[ttc multiscale] worst sum err/sum|t| {WORST['sum']:.2e} rel C {WORST['C']:.2e} foe {WORST['foe']:.2e}")
+
+
+def test_batched_workload_sampled(api):
+    """64 streams of uneven sizes, 16 f16 frames each, 4 levels, in one plan;
+    sampled pairs against the oracle."""
+    specs = synth.batched_specs()
+    vids = [s.render(device="cuda") for s in specs]
+    recs, picks = api.ttc_solve_batched(vids, 4)
+    assert picks.shape == (64 * 15,)
+    big = max(range(64), key=lambda i: specs[i].H * specs[i].W)
+    small = min(range(64), key=lambda i: specs[i].H * specs[i].W)
+    for s_i, t in ((big, 7), (small, 0), (5, 14)):
+        host = vids[s_i].cpu().numpy()
+        g = s_i * 15 + t
+        check_pair(recs[g * 4:(g + 1) * 4], picks[g], host[t], host[t + 1], 4, f"stream{s_i}")
+    print(f"[ttc batched] worst sum err/sum|t| {WORST['sum']:.2e} rel C {WORST['C']:.2e} foe {WORST['foe']:.2e}")

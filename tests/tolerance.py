@@ -1,0 +1,70 @@
+"""Tolerances for comparing GPU results with the FP64 oracle (test helper).
+
+Convolution (FP32 accumulation of K products per output, any order):
+    |y - y64| <= TAU_CONV * (|x| (*) |k|)[n]  element-wise, plus a norm-wise
+    ||y - y64||_inf <= TAU_CONV * ||y64||_inf.  TAU_CONV is the 1e-5 relative
+    target read against the sum of absolute products, since an element-wise
+    relative error is meaningless where y ~ 0.
+
+TTC sums: the GPU forms FP32 products, sums at most BLOCK terms per lane in
+plain FP32, reduces 64 lanes with a 6-level tree, and combines the blocks with
+TwoSum in the finishing pass.  The error of every sum is therefore bounded by
+    |s - s64| <= TAU_SUM * sum|terms|,
+TAU_SUM = (BLOCK + 6 + 8) * 2^-24 with BLOCK = 8 * 16 cubes per lane (the
+tallest band times eight columns), which also covers the rounding of the
+products and of G.  The bound on A, B, C follows from first-order perturbation
+of the normal equations, dv = -M^-1 (dM v + dr), with every sum moved by its
+own bound in the worst direction; TTC and FOE follow from C and (A, B).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as O
+
+TAU_CONV = 1e-5
+BLOCK = 8 * 16
+TAU_SUM = (BLOCK + 6 + 8) * 2.0 ** -24
+
+
+def abs_sums(P0, P1, level, H0, W0):
+    """sum |term| for each of the ten sums (oracle arrays, FP64)."""
+    ex, ey, et, g = O.level_terms(P0, P1, level, H0, W0)
+    prods = (ex * ex, ex * ey, ey * ey, g * ex, g * ey, g * g, ex * et, ey * et, g * et, et * et)
+    return np.array([float(np.abs(p).sum()) for p in prods])
+
+
+def solution_bounds(sums, abs_s, tau=TAU_SUM, safety=2.0):
+    """Worst-case first-order bounds (dA, dB, dC, dttc, dx0, dy0) from per-sum bounds tau * abs_s."""
+    s = [float(v) for v in sums]
+    M, rhs = O.ttc.normal_matrix(s)
+    M = np.array(M)
+    r = np.array(rhs)
+    v = np.linalg.solve(M, r)
+    Minv = np.linalg.inv(M)
+    # index of each sum in M (symmetric) and in r
+    where = {0: [(0, 0)], 1: [(0, 1), (1, 0)], 2: [(1, 1)], 3: [(0, 2), (2, 0)], 4: [(1, 2), (2, 1)], 5: [(2, 2)]}
+    dv = np.zeros(3)
+    for q in range(9):
+        dM = np.zeros((3, 3))
+        dr = np.zeros(3)
+        if q in where:
+            for (i, j) in where[q]:
+                dM[i, j] = 1.0
+        else:
+            dr[q - 6] = -1.0
+        sens = -Minv @ (dM @ v - dr)  # d v / d s_q  (M v = r, r = -[s6, s7, s8])
+        dv += np.abs(sens) * tau * abs_s[q]
+    dv *= safety
+    A, B, C = v
+    dttc = dv[2] / (C * C) if C != 0 else math.inf
+    dx0 = (dv[0] + abs(A / C) * dv[2]) / abs(C) if C != 0 else math.inf
+    dy0 = (dv[1] + abs(B / C) * dv[2]) / abs(C) if C != 0 else math.inf
+    return dict(A=dv[0], B=dv[1], C=dv[2], ttc=dttc, x0=dx0, y0=dy0)
+
+
+def conv_bound(x, k, mode):
+    """TAU_CONV * (|x| (*) |k|) with the oracle (FP64)."""
+    return TAU_CONV * O.conv(np.abs(np.asarray(x, dtype=np.float64)), np.abs(np.asarray(k, dtype=np.float64)), mode)
