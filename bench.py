@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-conv", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg, no conv sweep (for rocprofv3)")
+    ap.add_argument("--save-frames", default=None, help="render the batch, save it to this .npz and exit")
+    ap.add_argument("--load-frames", default=None, help="take the batch from a .npz written by --save-frames")
     return ap.parse_args()
 
 
@@ -174,9 +176,33 @@ def main():
 
     torch.cuda.set_device(0)
     n_cu = api.device_check(0)
-    vids = [s.render(device="cuda") for s in specs]
+    if args.profile:
+        # a plain device copy of known size (1 GiB read + 1 GiB written) whose
+        # FETCH_SIZE / WRITE_SIZE readings calibrate the counters of the fused kernel
+        src = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+    if args.load_frames:
+        # frames rendered earlier by --save-frames: this process launches no renderer kernels
+        with np.load(args.load_frames, allow_pickle=False) as z:
+            vids = [torch.from_numpy(z[f"s{i}"]).cuda() for i in range(len(specs))]
+        for s, v in zip(specs, vids):
+            assert tuple(v.shape) == (s.n_frames, s.H, s.W) and v.dtype == torch.float16
+    else:
+        vids = []
+        for s in specs:
+            vids.append(s.render(device="cuda"))
+            torch.cuda.synchronize()  # keep the queue shallow while rendering
     torch.cuda.synchronize()
-    print(f"[bench] rendered {len(vids)} streams", file=sys.stderr, flush=True)
+    print(f"[bench] {len(vids)} streams resident", file=sys.stderr, flush=True)
+    if args.save_frames:
+        np.savez(args.save_frames, **{f"s{i}": v.cpu().numpy() for i, v in enumerate(vids)})
+        print(f"[bench] saved frames to {args.save_frames}", file=sys.stderr, flush=True)
+        return
     plan = api.TTCPlan([api.seq_from_frames(v, LEVELS) for v in vids], torch.float16, keep=vids)
     plan.upload()
     frame_bytes, flops, pair_px = fused_work(specs, LEVELS, 2)

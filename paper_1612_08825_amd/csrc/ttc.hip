@@ -48,6 +48,36 @@ struct FusedArgs {
   float* partials;
 };
 
+// Every field of a descriptor read by a whole wave is the same in all lanes;
+// say so, so that all band geometry lives in scalar registers.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ SeqDesc uniform(const SeqDesc& s) {
+  SeqDesc d;
+  d.frame0 = reinterpret_cast<const void*>(uni((int64_t)reinterpret_cast<uintptr_t>(s.frame0)));
+  d.frame_stride = uni(s.frame_stride);
+  d.row_stride = uni(s.row_stride);
+  d.H = uni(s.H);
+  d.W = uni(s.W);
+  d.n_frames = uni(s.n_frames);
+  d.levels = uni(s.levels);
+  d.band_rows = uni(s.band_rows);
+  d.n_bands = uni(s.n_bands);
+  d.n_bgroups = uni(s.n_bgroups);
+  d.n_cw = uni(s.n_cw);
+  d.item_begin = uni(s.item_begin);
+  d.pair_begin = uni(s.pair_begin);
+  d.partial_begin = uni(s.partial_begin);
+  d.n_witems = uni(s.n_witems);
+  d.vec = uni(s.vec);
+  return d;
+}
+
 __device__ __forceinline__ SeqDesc seq_for_item(const FusedArgs& a, int64_t item) {
   if (a.table == nullptr) return a.inl;
   int lo = 0, hi = a.n_seqs - 1;
@@ -105,13 +135,16 @@ __device__ __forceinline__ void cubes_dispatch(bool edge, float (&acc)[10], cons
   else cubes<NC, false>(acc, hdp, hd, hsp, hs, hDp, hD, ncv, xb, y);
 }
 
+// Value of lane i + 1 of the same 16-lane row (DPP row_shl:1); lane 15 gets 0.
+__device__ __forceinline__ float from_right(float v) { return dpp_f32<0x101>(v); }
+
 // Horizontal quantities of one level row of NC columns, given its block sums U
 // (of S) and V (of D); the column right of the lane comes from lane + 1.
 template <int NC>
 __device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&V)[NC], float (&hs)[NC],
                                             float (&hd)[NC], float (&hD)[NC]) {
-  const float un = __shfl_down(U[0], 1, 16);
-  const float vn = __shfl_down(V[0], 1, 16);
+  const float un = from_right(U[0]);
+  const float vn = from_right(V[0]);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const float ur = (c + 1 < NC) ? U[c + 1] : un;
@@ -122,12 +155,184 @@ __device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&
   }
 }
 
-template <typename T, int LV, int RH>
-__global__ __launch_bounds__(256) void ttc_fused(FusedArgs a) {
+// One wave walks one band of one stream through all frames.  CHECK: the band
+// touches the bottom of the frame (rows may be missing) or the stream is not
+// vector-aligned; otherwise every walked row exists and the 8-pixel vector load
+// of a lane may run past column W into rows that exist.
+template <typename T, int LV, int RH, bool CHECK>
+__device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane, int lane, float* part,
+                                          int64_t witem) {
   constexpr int HALO = 1 << (LV - 1);
   constexpr int NR = RH + HALO;  // rows walked per band
+  const int li = lane & 15;
+  const int H = d.H, W = d.W;
+
+  // valid cube columns of this lane per level, and the cube-centre bases
+  int ncv[LV];
+  float xb[LV], yb[LV];
+  bool edge[LV];
+#pragma unroll
+  for (int l = 0; l < LV; ++l) {
+    const int wl = W >> l;
+    const int j0 = c_lane >> l;
+    int n = wl - 1 - j0;
+    n = n < 0 ? 0 : (n > (8 >> l) ? (8 >> l) : n);
+    ncv[l] = (li == 15) ? 0 : n;
+    xb[l] = (float)(j0 + 1) - (float)W / (float)(2 << l);
+    yb[l] = (float)(row0 >> l) - (float)H / (float)(2 << l);
+    const bool part_lane = ncv[l] > 0 && ncv[l] < (8 >> l);
+    edge[l] = __any(part_lane);
+  }
+
+  const int ncols = W - c_lane;  // pixels of this lane inside the image
+  const bool has_px = ncols > 0;
+  const uint32_t coff = (uint32_t)c_lane * (uint32_t)sizeof(T);
+  const int64_t rs_b = d.row_stride * (int64_t)sizeof(T);
+  const int64_t fs_b = d.frame_stride * (int64_t)sizeof(T);
+  const char* band0 = reinterpret_cast<const char*>(d.frame0) + (int64_t)row0 * rs_b;
+
+  auto load_row = [&](Raw8<T>& r, const char* frame_band, int w) {
+    const T* p = reinterpret_cast<const T*>(frame_band + (int64_t)w * rs_b + coff);
+    if constexpr (!CHECK) {
+      if (has_px) r.load(p);
+      else r.zero();
+    } else {
+      if (row0 + w < H && has_px) {
+        if (d.vec && ncols >= 8) r.load(p);
+        else r.load_partial(p, ncols < 8 ? ncols : 8);
+      } else {
+        r.zero();
+      }
+    }
+  };
+
+  Raw8<T> prv[NR];
+#pragma unroll
+  for (int w = 0; w < NR; ++w) load_row(prv[w], band0, w);
+
+  for (int k = 1; k < d.n_frames; ++k) {
+    const char* fk = band0 + (int64_t)k * fs_b;
+    float acc[LV][10];
+#pragma unroll
+    for (int l = 0; l < LV; ++l)
+#pragma unroll
+      for (int q = 0; q < 10; ++q) acc[l][q] = 0.f;
+
+    float hs0p[8], hd0p[8], hD0p[8];
+    float hs1p[4], hd1p[4], hD1p[4];
+    float hs2p[2], hd2p[2], hD2p[2];
+    float hs3p[1], hd3p[1], hD3p[1];
+
+#pragma unroll
+    for (int w = 0; w < NR; ++w) {
+      if (!CHECK || row0 + w < H) {
+        Raw8<T> cur;
+        load_row(cur, fk, w);
+        float pa[8], pb[8];
+        prv[w].unpack(pa);
+        cur.unpack(pb);
+        prv[w] = cur;
+        float S[8], D[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          S[c] = pa[c] + pb[c];
+          D[c] = pb[c] - pa[c];
+        }
+        float hs0[8], hd0[8], hD0[8];
+        horizontals<8>(S, D, hs0, hd0, hD0);
+        if (w >= 1 && w <= RH)
+          cubes_dispatch<8>(edge[0], acc[0], hd0p, hd0, hs0p, hs0, hD0p, hD0, ncv[0], xb[0], yb[0] + (float)w);
+        if constexpr (LV >= 2) {
+          if ((w & 1) == 1) {
+            float U1[4], V1[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              U1[c] = hs0p[2 * c] + hs0[2 * c];
+              V1[c] = hD0p[2 * c] + hD0[2 * c];
+            }
+            float hs1[4], hd1[4], hD1[4];
+            horizontals<4>(U1, V1, hs1, hd1, hD1);
+            const int lr1 = w >> 1;  // level-1 row just formed, counted from the band top
+            if (lr1 >= 1 && lr1 <= (RH >> 1))
+              cubes_dispatch<4>(edge[1], acc[1], hd1p, hd1, hs1p, hs1, hD1p, hD1, ncv[1], xb[1], yb[1] + (float)lr1);
+            if constexpr (LV >= 3) {
+              if ((w & 3) == 3) {
+                float U2[2], V2[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                  U2[c] = hs1p[2 * c] + hs1[2 * c];
+                  V2[c] = hD1p[2 * c] + hD1[2 * c];
+                }
+                float hs2[2], hd2[2], hD2[2];
+                horizontals<2>(U2, V2, hs2, hd2, hD2);
+                const int lr2 = w >> 2;
+                if (lr2 >= 1 && lr2 <= (RH >> 2))
+                  cubes_dispatch<2>(edge[2], acc[2], hd2p, hd2, hs2p, hs2, hD2p, hD2, ncv[2], xb[2],
+                                    yb[2] + (float)lr2);
+                if constexpr (LV >= 4) {
+                  if ((w & 7) == 7) {
+                    float U3[1], V3[1];
+                    U3[0] = hs2p[0] + hs2[0];
+                    V3[0] = hD2p[0] + hD2[0];
+                    float hs3[1], hd3[1], hD3[1];
+                    horizontals<1>(U3, V3, hs3, hd3, hD3);
+                    const int lr3 = w >> 3;
+                    if (lr3 >= 1 && lr3 <= (RH >> 3))
+                      cubes_dispatch<1>(edge[3], acc[3], hd3p, hd3, hs3p, hs3, hD3p, hD3, ncv[3], xb[3],
+                                        yb[3] + (float)lr3);
+                    hs3p[0] = hs3[0];
+                    hd3p[0] = hd3[0];
+                    hD3p[0] = hD3[0];
+                  }
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                  hs2p[c] = hs2[c];
+                  hd2p[c] = hd2[c];
+                  hD2p[c] = hD2[c];
+                }
+              }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              hs1p[c] = hs1[c];
+              hd1p[c] = hd1[c];
+              hD1p[c] = hD1[c];
+            }
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          hs0p[c] = hs0[c];
+          hd0p[c] = hd0[c];
+          hD0p[c] = hD0[c];
+        }
+      }
+    }
+
+    // one partial per (pair, level, wave): lanes that own no cube of a level
+    // contribute zero; lanes 0..9 store sum q = lane
+    const int p = k - 1;
+#pragma unroll
+    for (int l = 0; l < LV; ++l) {
+      const bool own = ncv[l] > 0;
+      float mine = 0.f;
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        const float v = wave64_allreduce(own ? acc[l][q] : 0.f);
+        mine = (lane == q) ? v : mine;
+      }
+      if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = mine;
+    }
+  }
+}
+
+template <typename T, int LV, int RH>
+__global__ __launch_bounds__(256) void ttc_fused(FusedArgs a) {
+  constexpr int NR = RH + (1 << (LV - 1));
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform: keep it (and all row geometry) in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15;
   const int seg = lane >> 4;
 
@@ -140,178 +345,29 @@ __global__ __launch_bounds__(256) void ttc_fused(FusedArgs a) {
   for (int64_t t = 0;; ++t) {
     const int64_t item = t * G + slot;
     if (item >= a.n_items) break;
-    const SeqDesc d = seq_for_item(a, item);
+    const SeqDesc d = uniform(seq_for_item(a, item));
     const int64_t local = item - d.item_begin;
     const int cw = (int)(local / d.n_bgroups);
     const int bg = (int)(local % d.n_bgroups);
     const int band = bg * kWavesPerItem + wave;
     const int64_t witem = local * kWavesPerItem + wave;
-    const int n_pairs = d.n_frames - 1;
     float* part = a.partials + d.partial_begin;
 
     if (band >= d.n_bands) {  // empty wave of the last band group: zero partials
+      const int n_pairs = d.n_frames - 1;
       for (int p = 0; p < n_pairs; ++p)
         for (int l = 0; l < LV; ++l)
           if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = 0.f;
       continue;
     }
-
-    const int H = d.H, W = d.W;
     const int row0 = band * RH;
     const int c_lane = cw * kWaveCols + seg * kSegCols + li * 8;
-
-    // valid cube columns of this lane per level, and the cube-centre bases
-    int ncv[LV];
-    float xb[LV], yb[LV];
-    bool edge[LV];
-#pragma unroll
-    for (int l = 0; l < LV; ++l) {
-      const int wl = W >> l;
-      const int j0 = c_lane >> l;
-      int n = wl - 1 - j0;
-      n = n < 0 ? 0 : (n > (8 >> l) ? (8 >> l) : n);
-      ncv[l] = (li == 15) ? 0 : n;
-      xb[l] = (float)(j0 + 1) - (float)W / (float)(2 << l);
-      yb[l] = (float)(row0 >> l) - (float)H / (float)(2 << l);
-      const bool part_lane = ncv[l] > 0 && ncv[l] < (8 >> l);
-      edge[l] = __any(part_lane);
-    }
-
-    const T* f0 = reinterpret_cast<const T*>(d.frame0);
-    const int ncols = W - c_lane;  // pixels of this lane inside the image
-    const bool vec = d.vec != 0;  // uniform: 8-pixel chunks are 8/16-byte aligned
-    auto load_row = [&](Raw8<T>& r, const T* frame, int row) {
-      const T* p = frame + (int64_t)row * d.row_stride + c_lane;
-      if (vec && ncols >= 8) r.load(p);
-      else if (ncols > 0) r.load_partial(p, ncols < 8 ? ncols : 8);
-      else r.zero();
-    };
-
-    Raw8<T> prv[NR];
-#pragma unroll
-    for (int w = 0; w < NR; ++w) {
-      if (row0 + w < H) load_row(prv[w], f0, row0 + w);
-      else prv[w].zero();
-    }
-
-    for (int k = 1; k < d.n_frames; ++k) {
-      const T* fk = f0 + (int64_t)k * d.frame_stride;
-      float acc[LV][10];
-#pragma unroll
-      for (int l = 0; l < LV; ++l)
-#pragma unroll
-        for (int q = 0; q < 10; ++q) acc[l][q] = 0.f;
-
-      float hs0p[8], hd0p[8], hD0p[8];
-      float hs1p[4], hd1p[4], hD1p[4];
-      float hs2p[2], hd2p[2], hD2p[2];
-      float hs3p[1], hd3p[1], hD3p[1];
-
-#pragma unroll
-      for (int w = 0; w < NR; ++w) {
-        if (row0 + w < H) {
-          Raw8<T> cur;
-          load_row(cur, fk, row0 + w);
-          float pa[8], pb[8];
-          prv[w].unpack(pa);
-          cur.unpack(pb);
-          prv[w] = cur;
-          float S[8], D[8];
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            S[c] = pa[c] + pb[c];
-            D[c] = pb[c] - pa[c];
-          }
-          float hs0[8], hd0[8], hD0[8];
-          horizontals<8>(S, D, hs0, hd0, hD0);
-          if (w >= 1 && w <= RH)
-            cubes_dispatch<8>(edge[0], acc[0], hd0p, hd0, hs0p, hs0, hD0p, hD0, ncv[0], xb[0], yb[0] + (float)w);
-          if constexpr (LV >= 2) {
-            if ((w & 1) == 1) {
-              float U1[4], V1[4];
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                U1[c] = hs0p[2 * c] + hs0[2 * c];
-                V1[c] = hD0p[2 * c] + hD0[2 * c];
-              }
-              float hs1[4], hd1[4], hD1[4];
-              horizontals<4>(U1, V1, hs1, hd1, hD1);
-              constexpr int r1 = 0;  // placeholder to keep the structure readable
-              (void)r1;
-              const int lr1 = w >> 1;
-              if (lr1 >= 1 && lr1 <= (RH >> 1))
-                cubes_dispatch<4>(edge[1], acc[1], hd1p, hd1, hs1p, hs1, hD1p, hD1, ncv[1], xb[1],
-                                  yb[1] + (float)lr1);
-              if constexpr (LV >= 3) {
-                if ((w & 3) == 3) {
-                  float U2[2], V2[2];
-#pragma unroll
-                  for (int c = 0; c < 2; ++c) {
-                    U2[c] = hs1p[2 * c] + hs1[2 * c];
-                    V2[c] = hD1p[2 * c] + hD1[2 * c];
-                  }
-                  float hs2[2], hd2[2], hD2[2];
-                  horizontals<2>(U2, V2, hs2, hd2, hD2);
-                  const int lr2 = w >> 2;
-                  if (lr2 >= 1 && lr2 <= (RH >> 2))
-                    cubes_dispatch<2>(edge[2], acc[2], hd2p, hd2, hs2p, hs2, hD2p, hD2, ncv[2], xb[2],
-                                      yb[2] + (float)lr2);
-                  if constexpr (LV >= 4) {
-                    if ((w & 7) == 7) {
-                      float U3[1], V3[1];
-                      U3[0] = hs2p[0] + hs2[0];
-                      V3[0] = hD2p[0] + hD2[0];
-                      float hs3[1], hd3[1], hD3[1];
-                      horizontals<1>(U3, V3, hs3, hd3, hD3);
-                      const int lr3 = w >> 3;
-                      if (lr3 >= 1 && lr3 <= (RH >> 3))
-                        cubes_dispatch<1>(edge[3], acc[3], hd3p, hd3, hs3p, hs3, hD3p, hD3, ncv[3], xb[3],
-                                          yb[3] + (float)lr3);
-                      hs3p[0] = hs3[0];
-                      hd3p[0] = hd3[0];
-                      hD3p[0] = hD3[0];
-                    }
-                  }
-#pragma unroll
-                  for (int c = 0; c < 2; ++c) {
-                    hs2p[c] = hs2[c];
-                    hd2p[c] = hd2[c];
-                    hD2p[c] = hD2[c];
-                  }
-                }
-              }
-#pragma unroll
-              for (int c = 0; c < 4; ++c) {
-                hs1p[c] = hs1[c];
-                hd1p[c] = hd1[c];
-                hD1p[c] = hD1[c];
-              }
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            hs0p[c] = hs0[c];
-            hd0p[c] = hd0[c];
-            hD0p[c] = hD0[c];
-          }
-        }
-      }
-
-      // one partial per (pair, level, wave): lanes that own no cube of a level
-      // contribute zero; lanes 0..9 store sum q = lane
-      const int p = k - 1;
-#pragma unroll
-      for (int l = 0; l < LV; ++l) {
-        const bool own = ncv[l] > 0;
-        float mine = 0.f;
-#pragma unroll
-        for (int q = 0; q < 10; ++q) {
-          const float v = wave64_allreduce(own ? acc[l][q] : 0.f);
-          mine = (lane == q) ? v : mine;
-        }
-        if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = mine;
-      }
-    }
+    // fast path: all walked rows exist and a vector load running up to 7 pixels
+    // past column W of the last walked row stays inside the frame
+    const int64_t below = (int64_t)d.H - row0 - NR;
+    const bool fast = d.vec && below >= 1 && below * d.row_stride >= 8;
+    if (fast) band_walk<T, LV, RH, false>(d, row0, c_lane, lane, part, witem);
+    else band_walk<T, LV, RH, true>(d, row0, c_lane, lane, part, witem);
   }
 }
 
