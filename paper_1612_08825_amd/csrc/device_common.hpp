@@ -9,6 +9,21 @@
 
 namespace ttc {
 
+// Pointers into device memory given to the kernels are generic; reading through
+// a generic pointer compiles to FLAT instructions, whose completion is counted
+// together with LDS operations, so every wait on an LDS read would also wait
+// for all outstanding frame loads.  Loads and stores of frame data and partial
+// sums therefore go through explicitly global (address space 1) pointers.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)(p);
+}
+template <typename T> __device__ __forceinline__ gptr<const T> as_global(const T* p) {
+  return (gptr<const T>)(p);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 // ---- scalar element conversion ---------------------------------------------
 template <typename T> __device__ __forceinline__ float to_f32(T v);
 template <> __device__ __forceinline__ float to_f32<float>(float v) { return v; }
@@ -24,15 +39,16 @@ template <> struct Raw8<uint8_t> {
   uint32_t d[2];
   __device__ __forceinline__ void zero() { d[0] = d[1] = 0u; }
   __device__ __forceinline__ void load(const uint8_t* p) {
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    const u32x2 v = *as_global(reinterpret_cast<const u32x2*>(p));
     d[0] = v.x;
     d[1] = v.y;
   }
   __device__ __forceinline__ void load_partial(const uint8_t* p, int n) {
+    const gptr<const uint8_t> g = as_global(p);
     uint32_t w[2] = {0u, 0u};
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-      if (c < n) w[c >> 2] |= (uint32_t)p[c] << (8 * (c & 3));
+      if (c < n) w[c >> 2] |= (uint32_t)g[c] << (8 * (c & 3));
     d[0] = w[0];
     d[1] = w[1];
   }
@@ -46,14 +62,14 @@ template <> struct Raw8<_Float16> {
   uint32_t d[4];
   __device__ __forceinline__ void zero() { d[0] = d[1] = d[2] = d[3] = 0u; }
   __device__ __forceinline__ void load(const _Float16* p) {
-    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    const u32x4 v = *as_global(reinterpret_cast<const u32x4*>(p));
     d[0] = v.x;
     d[1] = v.y;
     d[2] = v.z;
     d[3] = v.w;
   }
   __device__ __forceinline__ void load_partial(const _Float16* p, int n) {
-    const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
+    const gptr<const uint16_t> q = as_global(reinterpret_cast<const uint16_t*>(p));
     uint32_t w[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
     for (int c = 0; c < 8; ++c)

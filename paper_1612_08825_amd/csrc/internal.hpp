@@ -41,9 +41,10 @@ hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, v
 
 // ---------------------------------------------------------------- fused TTC
 // One entry of the device work table: a video stream and where its work and
-// results go.  The fused pass covers the stream with "items": a group of four
-// vertically adjacent bands (one per wave) of kRowsPerBand rows by one
-// column-wave of 480 owned base columns (4 segments x 15 lanes x 8 columns).
+// results go.  The fused pass covers the stream with work items of one wave
+// each: a band of `band_rows` base rows by one column-wave of 480 owned base
+// columns (4 segments x 15 lanes x 8 columns).  Items are numbered
+// column-wave-major, band-minor, so consecutive items are vertically adjacent.
 struct SeqDesc {
   const void* frame0;
   int64_t frame_stride;   // elements
@@ -53,23 +54,22 @@ struct SeqDesc {
   int32_t levels;
   int32_t band_rows;      // owned base rows per band (one wave)
   int32_t n_bands;        // ceil(H / band_rows)
-  int32_t n_bgroups;      // ceil(n_bands / 4)
   int32_t n_cw;           // ceil(ceil((W - 1) / 120) / 4)
+  int32_t n_witems;       // work items (waves) per (pair, level) = n_bands * n_cw
   int64_t item_begin;     // first work item of this stream (prefix over streams)
   int64_t pair_begin;     // first global pair index of this stream
   int64_t partial_begin;  // first float of this stream's partial sums
-  int32_t n_witems;       // wave items per (pair, level) = n_bgroups * n_cw * 4
   int32_t vec;            // 1: every 8-pixel lane chunk is aligned for one vector load
+  int32_t pad;
 };
 
 constexpr int kSegCols = 120;         // owned base columns per 16-lane segment
 constexpr int kWaveCols = 4 * kSegCols;
-constexpr int kWavesPerItem = 4;
 
 struct FusedLaunch {
   int dt;           // TC_U8 or TC_F16
   int levels;       // 1..4
-  int band_rows;    // 8, 16 or 24
+  int band_rows;    // 8, 16 or 32
   const SeqDesc* table;  // device table, or nullptr to use `inl`
   int n_seqs;
   SeqDesc inl;

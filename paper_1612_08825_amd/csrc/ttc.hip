@@ -7,14 +7,16 @@
 // level choice.
 //
 // How (one persistent launch, then a small finishing launch):
-//   * A wave owns a band of kRowsPerBand base rows and 480 columns, split in
-//     four 16-lane segments; lane i of a segment holds 8 adjacent base
-//     columns (one level-3 column).  Lane 15 of each segment only provides its
-//     left column to lane 14 (the segment owns 120 columns).
+//   * A work item is one wave: a band of RH base rows by 480 columns, split in
+//     four 16-lane segments; lane i of a segment holds 8 adjacent base columns
+//     (one level-3 column).  Lane 15 of each segment only provides its left
+//     column to lane 14 (the segment owns 120 columns).
 //   * The wave walks the stream's frames in time.  The previous frame's band
-//     stays in registers in its packed u8 / f16 form, so every frame is read
-//     from memory once; each new frame row is combined with the stored one as
-//     the temporal sum S = P0 + P1 and difference D = P1 - P0.
+//     stays in LDS in its packed u8 / f16 form (each lane reads and writes only
+//     its own slots), so every frame is read from memory once; each new frame
+//     row is combined with the stored one as the temporal sum S = P0 + P1 and
+//     difference D = P1 - P0.  The current frame's rows are prefetched a few
+//     rows ahead into registers.
 //   * Rows are walked top to bottom.  Horizontal neighbour sums/differences of
 //     S and D give the derivative cube by one more vertical step.  Because the
 //     pyramid is linear, the 2x2 sums of S and D at even columns *are* the next
@@ -32,6 +34,8 @@
 //   hx = 2^(3l+2) E_x (per base px), hy likewise, ht = 2^(2l+2) E_t,
 //   g = x_l hx + y_l hy = 2^(2l+2) G with x_l, y_l the cube centre in level pixels.
 #include <math.h>
+
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "internal.hpp"
@@ -68,34 +72,47 @@ __device__ __forceinline__ SeqDesc uniform(const SeqDesc& s) {
   d.levels = uni(s.levels);
   d.band_rows = uni(s.band_rows);
   d.n_bands = uni(s.n_bands);
-  d.n_bgroups = uni(s.n_bgroups);
   d.n_cw = uni(s.n_cw);
   d.item_begin = uni(s.item_begin);
   d.pair_begin = uni(s.pair_begin);
   d.partial_begin = uni(s.partial_begin);
   d.n_witems = uni(s.n_witems);
   d.vec = uni(s.vec);
+  d.pad = 0;
+  return d;
+}
+
+// Copy one table entry through a global pointer, a dword at a time.
+__device__ __forceinline__ SeqDesc load_desc(gptr<const SeqDesc> p) {
+  static_assert(sizeof(SeqDesc) % 4 == 0, "descriptor must be whole dwords");
+  SeqDesc d;
+  const gptr<const uint32_t> src = (gptr<const uint32_t>)p;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&d);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(SeqDesc) / 4); ++i) dst[i] = src[i];
   return d;
 }
 
 __device__ __forceinline__ SeqDesc seq_for_item(const FusedArgs& a, int64_t item) {
   if (a.table == nullptr) return a.inl;
+  const gptr<const SeqDesc> tab = as_global(a.table);
   int lo = 0, hi = a.n_seqs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (a.table[mid].item_begin <= item) lo = mid; else hi = mid - 1;
+    if (tab[mid].item_begin <= item) lo = mid; else hi = mid - 1;
   }
-  return a.table[lo];
+  return load_desc(tab + lo);
 }
 
 __device__ __forceinline__ SeqDesc seq_for_pair(const FusedArgs& a, int64_t pair) {
   if (a.table == nullptr) return a.inl;
+  const gptr<const SeqDesc> tab = as_global(a.table);
   int lo = 0, hi = a.n_seqs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (a.table[mid].pair_begin <= pair) lo = mid; else hi = mid - 1;
+    if (tab[mid].pair_begin <= pair) lo = mid; else hi = mid - 1;
   }
-  return a.table[lo];
+  return load_desc(tab + lo);
 }
 
 // Accumulate the cubes of one row of one level.  hd*, hs*, hD* are the horizontal
@@ -155,15 +172,52 @@ __device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&
   }
 }
 
+// Sum over all 64 lanes, delivered to the lanes of the last 16-lane row
+// (lanes 48..63): a DPP butterfly inside each row, then the row totals are
+// chained with row_bcast15 (row r+1 += last lane of row r, rows 1 and 3) and
+// row_bcast31 (rows 2, 3 += lane 31).
+__device__ __forceinline__ float wave_total_row3(float v) {
+  v = row16_allreduce(v);
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
+  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
+  return v;
+}
+
+// The rows of a band are walked in groups of G rows (8 with four levels, so that
+// every level's row pattern repeats inside a group; 4 otherwise).  Rows walked:
+// the band plus the halo of 2^(LV-1) rows below it, rounded up to whole groups.
+template <int LV> constexpr int row_group() { return LV >= 4 ? 8 : 4; }
+template <int LV, int RH> constexpr int walked_rows() {
+  return ((RH + (1 << (LV - 1))) + row_group<LV>() - 1) / row_group<LV>() * row_group<LV>();
+}
+
+constexpr int kPartialChunk = 16;  // pairs whose partial sums are staged in LDS before the write-out
+// s_waitcnt immediate for vmcnt(0) with expcnt and lgkmcnt left at their maxima
+// (gfx9 encoding: vmcnt[3:0] and [15:14], expcnt[6:4], lgkmcnt[11:8]).
+constexpr int kWaitVmcntZero = 0x0F70;
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 // One wave walks one band of one stream through all frames.  CHECK: the band
 // touches the bottom of the frame (rows may be missing) or the stream is not
 // vector-aligned; otherwise every walked row exists and the 8-pixel vector load
-// of a lane may run past column W into rows that exist.
+// of a lane may run past column W into rows that exist.  `prev` is this wave's
+// LDS band store, [NR][64] packed rows.
+//
+// Rows are prefetched G rows ahead through a ring of G registers that crosses
+// frame boundaries: while the last rows of frame k are processed, the first
+// rows of frame k+1 are already in flight.
 template <typename T, int LV, int RH, bool CHECK>
 __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane, int lane, float* part,
-                                          int64_t witem) {
-  constexpr int HALO = 1 << (LV - 1);
-  constexpr int NR = RH + HALO;  // rows walked per band
+                                          int64_t witem, Raw8<T>* prev, float* pbuf) {
+  constexpr int G = row_group<LV>();  // depth of the prefetch ring
+  constexpr int NR = walked_rows<LV, RH>();
   const int li = lane & 15;
   const int H = d.H, W = d.W;
 
@@ -185,8 +239,11 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
   }
 
   const int ncols = W - c_lane;  // pixels of this lane inside the image
-  const bool has_px = ncols > 0;
-  const uint32_t coff = (uint32_t)c_lane * (uint32_t)sizeof(T);
+  // Lanes right of the image read the last aligned chunk of the row instead:
+  // every load is unconditional (so the compiler can count loads in flight),
+  // and what those lanes hold only reaches cubes that are not valid.
+  const int c_load = c_lane < W ? c_lane : ((W - 1) >> 3) << 3;
+  const uint32_t coff = (uint32_t)c_load * (uint32_t)sizeof(T);
   const int64_t rs_b = d.row_stride * (int64_t)sizeof(T);
   const int64_t fs_b = d.frame_stride * (int64_t)sizeof(T);
   const char* band0 = reinterpret_cast<const char*>(d.frame0) + (int64_t)row0 * rs_b;
@@ -194,11 +251,12 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
   auto load_row = [&](Raw8<T>& r, const char* frame_band, int w) {
     const T* p = reinterpret_cast<const T*>(frame_band + (int64_t)w * rs_b + coff);
     if constexpr (!CHECK) {
-      if (has_px) r.load(p);
-      else r.zero();
+      r.load(p);
     } else {
-      if (row0 + w < H && has_px) {
-        if (d.vec && ncols >= 8) r.load(p);
+      const int row = row0 + w;
+      if (row < H && ncols > 0) {
+        // a vector load may overrun column W only where a next row exists
+        if (d.vec && (ncols >= 8 || row < H - 1)) r.load(p);
         else r.load_partial(p, ncols < 8 ? ncols : 8);
       } else {
         r.zero();
@@ -206,12 +264,21 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
     }
   };
 
-  Raw8<T> prv[NR];
+  // frame 0 into the band store, the first group of frame 1 into the ring
+  for (int w = 0; w < NR; ++w) {
+    Raw8<T> r;
+    load_row(r, band0, w);
+    prev[w * 64 + lane] = r;
+  }
+  Raw8<T> ahead[G];
 #pragma unroll
-  for (int w = 0; w < NR; ++w) load_row(prv[w], band0, w);
+  for (int i = 0; i < G; ++i) load_row(ahead[i], band0 + fs_b, i);
 
   for (int k = 1; k < d.n_frames; ++k) {
     const char* fk = band0 + (int64_t)k * fs_b;
+    // the frame whose first group is prefetched during this frame's last group
+    // (this frame again after the last one: a harmless in-bounds reload)
+    const char* fnext = (k + 1 < d.n_frames) ? fk + fs_b : fk;
     float acc[LV][10];
 #pragma unroll
     for (int l = 0; l < LV; ++l)
@@ -223,27 +290,33 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
     float hs2p[2], hd2p[2], hD2p[2];
     float hs3p[1], hd3p[1], hD3p[1];
 
+    // the whole walk of a frame is unrolled: the loads in flight are then only
+    // carried across the frame loop's back edge (the compiler cannot keep a
+    // partial wait for loads carried across a loop back edge)
+    {
+      static_for<0, NR>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        constexpr int i = w % G;
+        const Raw8<T> cur = ahead[i];
+        if constexpr (w + G < NR) load_row(ahead[i], fk, w + G);
+        else load_row(ahead[i], fnext, w + G - NR);
+        if (!CHECK || row0 + w < H) {
+          const Raw8<T> old = prev[w * 64 + lane];
+          prev[w * 64 + lane] = cur;
+          float pa[8], pb[8];
+          old.unpack(pa);
+          cur.unpack(pb);
+          float S[8], D[8];
 #pragma unroll
-    for (int w = 0; w < NR; ++w) {
-      if (!CHECK || row0 + w < H) {
-        Raw8<T> cur;
-        load_row(cur, fk, w);
-        float pa[8], pb[8];
-        prv[w].unpack(pa);
-        cur.unpack(pb);
-        prv[w] = cur;
-        float S[8], D[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          S[c] = pa[c] + pb[c];
-          D[c] = pb[c] - pa[c];
-        }
-        float hs0[8], hd0[8], hD0[8];
-        horizontals<8>(S, D, hs0, hd0, hD0);
-        if (w >= 1 && w <= RH)
-          cubes_dispatch<8>(edge[0], acc[0], hd0p, hd0, hs0p, hs0, hD0p, hD0, ncv[0], xb[0], yb[0] + (float)w);
-        if constexpr (LV >= 2) {
-          if ((w & 1) == 1) {
+          for (int c = 0; c < 8; ++c) {
+            S[c] = pa[c] + pb[c];
+            D[c] = pb[c] - pa[c];
+          }
+          float hs0[8], hd0[8], hD0[8];
+          horizontals<8>(S, D, hs0, hd0, hD0);
+          if constexpr (w >= 1 && w <= RH)
+            cubes_dispatch<8>(edge[0], acc[0], hd0p, hd0, hs0p, hs0, hD0p, hD0, ncv[0], xb[0], yb[0] + (float)w);
+          if constexpr (LV >= 2 && (i & 1) == 1) {
             float U1[4], V1[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -252,45 +325,40 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
             }
             float hs1[4], hd1[4], hD1[4];
             horizontals<4>(U1, V1, hs1, hd1, hD1);
-            const int lr1 = w >> 1;  // level-1 row just formed, counted from the band top
-            if (lr1 >= 1 && lr1 <= (RH >> 1))
+            constexpr int lr1 = w >> 1;  // level-1 row just formed, counted from the band top
+            if constexpr (lr1 >= 1 && lr1 <= (RH >> 1))
               cubes_dispatch<4>(edge[1], acc[1], hd1p, hd1, hs1p, hs1, hD1p, hD1, ncv[1], xb[1], yb[1] + (float)lr1);
-            if constexpr (LV >= 3) {
-              if ((w & 3) == 3) {
-                float U2[2], V2[2];
+            if constexpr (LV >= 3 && (i & 3) == 3) {
+              float U2[2], V2[2];
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                  U2[c] = hs1p[2 * c] + hs1[2 * c];
-                  V2[c] = hD1p[2 * c] + hD1[2 * c];
-                }
-                float hs2[2], hd2[2], hD2[2];
-                horizontals<2>(U2, V2, hs2, hd2, hD2);
-                const int lr2 = w >> 2;
-                if (lr2 >= 1 && lr2 <= (RH >> 2))
-                  cubes_dispatch<2>(edge[2], acc[2], hd2p, hd2, hs2p, hs2, hD2p, hD2, ncv[2], xb[2],
-                                    yb[2] + (float)lr2);
-                if constexpr (LV >= 4) {
-                  if ((w & 7) == 7) {
-                    float U3[1], V3[1];
-                    U3[0] = hs2p[0] + hs2[0];
-                    V3[0] = hD2p[0] + hD2[0];
-                    float hs3[1], hd3[1], hD3[1];
-                    horizontals<1>(U3, V3, hs3, hd3, hD3);
-                    const int lr3 = w >> 3;
-                    if (lr3 >= 1 && lr3 <= (RH >> 3))
-                      cubes_dispatch<1>(edge[3], acc[3], hd3p, hd3, hs3p, hs3, hD3p, hD3, ncv[3], xb[3],
-                                        yb[3] + (float)lr3);
-                    hs3p[0] = hs3[0];
-                    hd3p[0] = hd3[0];
-                    hD3p[0] = hD3[0];
-                  }
-                }
+              for (int c = 0; c < 2; ++c) {
+                U2[c] = hs1p[2 * c] + hs1[2 * c];
+                V2[c] = hD1p[2 * c] + hD1[2 * c];
+              }
+              float hs2[2], hd2[2], hD2[2];
+              horizontals<2>(U2, V2, hs2, hd2, hD2);
+              constexpr int lr2 = w >> 2;
+              if constexpr (lr2 >= 1 && lr2 <= (RH >> 2))
+                cubes_dispatch<2>(edge[2], acc[2], hd2p, hd2, hs2p, hs2, hD2p, hD2, ncv[2], xb[2], yb[2] + (float)lr2);
+              if constexpr (LV >= 4 && (i & 7) == 7) {
+                float U3[1], V3[1];
+                U3[0] = hs2p[0] + hs2[0];
+                V3[0] = hD2p[0] + hD2[0];
+                float hs3[1], hd3[1], hD3[1];
+                horizontals<1>(U3, V3, hs3, hd3, hD3);
+                constexpr int lr3 = w >> 3;
+                if constexpr (lr3 >= 1 && lr3 <= (RH >> 3))
+                  cubes_dispatch<1>(edge[3], acc[3], hd3p, hd3, hs3p, hs3, hD3p, hD3, ncv[3], xb[3],
+                                    yb[3] + (float)lr3);
+                hs3p[0] = hs3[0];
+                hd3p[0] = hd3[0];
+                hD3p[0] = hD3[0];
+              }
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                  hs2p[c] = hs2[c];
-                  hd2p[c] = hd2[c];
-                  hD2p[c] = hD2[c];
-                }
+              for (int c = 0; c < 2; ++c) {
+                hs2p[c] = hs2[c];
+                hd2p[c] = hd2[c];
+                hD2p[c] = hD2[c];
               }
             }
 #pragma unroll
@@ -300,39 +368,58 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
               hD1p[c] = hD1[c];
             }
           }
-        }
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          hs0p[c] = hs0[c];
-          hd0p[c] = hd0[c];
-          hD0p[c] = hD0[c];
+          for (int c = 0; c < 8; ++c) {
+            hs0p[c] = hs0[c];
+            hd0p[c] = hd0[c];
+            hD0p[c] = hD0[c];
+          }
         }
-      }
+      });
     }
 
     // one partial per (pair, level, wave): lanes that own no cube of a level
-    // contribute zero; lanes 0..9 store sum q = lane
+    // contribute zero; lanes 48..57 hold sum q = lane - 48.  Partials are staged
+    // in LDS and written out every kPartialChunk pairs, so that stores are
+    // rarely in flight while the next rows are being prefetched.
     const int p = k - 1;
+    const int pc = p % kPartialChunk;
 #pragma unroll
     for (int l = 0; l < LV; ++l) {
       const bool own = ncv[l] > 0;
       float mine = 0.f;
 #pragma unroll
       for (int q = 0; q < 10; ++q) {
-        const float v = wave64_allreduce(own ? acc[l][q] : 0.f);
-        mine = (lane == q) ? v : mine;
+        const float v = wave_total_row3(own ? acc[l][q] : 0.f);
+        mine = (lane == 48 + q) ? v : mine;
       }
-      if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = mine;
+      if (lane >= 48 && lane < 58) pbuf[(pc * LV + l) * 10 + (lane - 48)] = mine;
+    }
+    if (pc == kPartialChunk - 1 || k == d.n_frames - 1) {
+      __syncthreads();
+      const int p0 = p - pc;
+      const int n = (pc + 1) * LV * 10;
+      for (int idx = lane; idx < n; idx += 64) {
+        const int pl = idx / 10;  // (pair in chunk) * LV + level
+        const int q = idx - pl * 10;
+        as_global(part)[((int64_t)(p0 * LV + pl) * d.n_witems + witem) * 10 + q] = pbuf[idx];
+      }
+      // Loads and stores share one completion counter and may complete out of
+      // order with respect to each other; with a store possibly in flight, every
+      // later wait for a prefetched row would have to drain the counter.  Drain
+      // it here, once per chunk, so the row loop's waits can stay partial.
+      __builtin_amdgcn_s_waitcnt(kWaitVmcntZero);
+      __syncthreads();
     }
   }
 }
 
 template <typename T, int LV, int RH>
-__global__ __launch_bounds__(256) void ttc_fused(FusedArgs a) {
-  constexpr int NR = RH + (1 << (LV - 1));
-  const int lane = threadIdx.x & 63;
-  // the wave index is uniform: keep it (and all row geometry) in scalar registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
+  constexpr int NR = walked_rows<LV, RH>();
+  __shared__ Raw8<T> prev[NR * 64];
+  __shared__ float pbuf[kPartialChunk * LV * 10];
+  const int lane = threadIdx.x;
   const int li = lane & 15;
   const int seg = lane >> 4;
 
@@ -346,28 +433,18 @@ __global__ __launch_bounds__(256) void ttc_fused(FusedArgs a) {
     const int64_t item = t * G + slot;
     if (item >= a.n_items) break;
     const SeqDesc d = uniform(seq_for_item(a, item));
-    const int64_t local = item - d.item_begin;
-    const int cw = (int)(local / d.n_bgroups);
-    const int bg = (int)(local % d.n_bgroups);
-    const int band = bg * kWavesPerItem + wave;
-    const int64_t witem = local * kWavesPerItem + wave;
+    const int64_t local = item - d.item_begin;  // = cw * n_bands + band
+    const int cw = (int)(local / d.n_bands);
+    const int band = (int)(local % d.n_bands);
     float* part = a.partials + d.partial_begin;
-
-    if (band >= d.n_bands) {  // empty wave of the last band group: zero partials
-      const int n_pairs = d.n_frames - 1;
-      for (int p = 0; p < n_pairs; ++p)
-        for (int l = 0; l < LV; ++l)
-          if (lane < 10) part[((int64_t)(p * LV + l) * d.n_witems + witem) * 10 + lane] = 0.f;
-      continue;
-    }
     const int row0 = band * RH;
     const int c_lane = cw * kWaveCols + seg * kSegCols + li * 8;
     // fast path: all walked rows exist and a vector load running up to 7 pixels
     // past column W of the last walked row stays inside the frame
     const int64_t below = (int64_t)d.H - row0 - NR;
     const bool fast = d.vec && below >= 1 && below * d.row_stride >= 8;
-    if (fast) band_walk<T, LV, RH, false>(d, row0, c_lane, lane, part, witem);
-    else band_walk<T, LV, RH, true>(d, row0, c_lane, lane, part, witem);
+    if (fast) band_walk<T, LV, RH, false>(d, row0, c_lane, lane, part, local, prev, pbuf);
+    else band_walk<T, LV, RH, true>(d, row0, c_lane, lane, part, local, prev, pbuf);
   }
 }
 
@@ -469,7 +546,8 @@ __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __r
     float hi[10], lo[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) hi[q] = lo[q] = 0.f;
-    const float* base = a.partials + d.partial_begin + (p * LV + l) * (int64_t)d.n_witems * 10;
+    const gptr<const float> base =
+        as_global(a.partials + d.partial_begin + (p * LV + l) * (int64_t)d.n_witems * 10);
     for (int w = tid; w < d.n_witems; w += 256) {
 #pragma unroll
       for (int q = 0; q < 10; ++q) comp_add(hi[q], lo[q], base[(int64_t)w * 10 + q]);
@@ -537,10 +615,11 @@ FusedArgs make_args(const FusedLaunch& f) {
 template <typename T, int LV>
 hipError_t fused_rh(const FusedLaunch& f, hipStream_t s) {
   const FusedArgs a = make_args(f);
-  const dim3 grid((unsigned)f.grid), block(256);
+  const dim3 grid((unsigned)f.grid), block(64);
   switch (f.band_rows) {
     case 8: hipLaunchKernelGGL((ttc_fused<T, LV, 8>), grid, block, 0, s, a); break;
     case 16: hipLaunchKernelGGL((ttc_fused<T, LV, 16>), grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL((ttc_fused<T, LV, 32>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -560,8 +639,8 @@ hipError_t fused_lv(const FusedLaunch& f, hipStream_t s) {
 }  // namespace
 
 bool fused_variant_exists(int dt, int levels, int band_rows) {
-  return (dt == TC_U8 || dt == TC_F16) && levels >= 1 && levels <= 4 && (band_rows == 8 || band_rows == 16) &&
-         band_rows >= (1 << (levels - 1));
+  return (dt == TC_U8 || dt == TC_F16) && levels >= 1 && levels <= 4 &&
+         (band_rows == 8 || band_rows == 16 || band_rows == 32);
 }
 
 hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s) {

@@ -4,6 +4,7 @@
 // tables) and the small tap copy of integer convolutions.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -297,6 +298,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // sweep of the fused pass; a multiple of 2^(levels-1) for every entry.
 int choose_band_rows(int dtype, int levels) {
   (void)levels;
+  if (const char* e = getenv("TC_BAND_ROWS")) {
+    const int v = atoi(e);
+    if (v == 8 || v == 16 || v == 32) return v;
+  }
   return dtype == TC_U8 ? 16 : 8;
 }
 
@@ -331,16 +336,16 @@ void fill_desc(SeqDesc& d, const tc_seq& q, int dtype, int band_rows) {
   d.levels = q.levels;
   d.band_rows = band_rows;
   d.n_bands = (q.H + band_rows - 1) / band_rows;
-  d.n_bgroups = (d.n_bands + kWavesPerItem - 1) / kWavesPerItem;
   const int n_seg = (q.W - 1 + kSegCols - 1) / kSegCols;
   d.n_cw = (n_seg + 3) / 4;
-  d.n_witems = d.n_bgroups * d.n_cw * kWavesPerItem;
+  d.n_witems = d.n_bands * d.n_cw;
+  d.pad = 0;
   d.vec = vector_ok(q, dtype);
 }
 
 int persistent_grid(int64_t n_items) {
   const int n_cu = current_cu_count();
-  int64_t g = std::min<int64_t>(n_items, (int64_t)n_cu * 8);
+  int64_t g = std::min<int64_t>(n_items, (int64_t)n_cu * 16);
   if (g >= 8) g -= g % 8;
   return (int)std::max<int64_t>(g, 1);
 }
@@ -380,7 +385,7 @@ extern "C" int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dt
     d.item_begin = items;
     d.pair_begin = pairs;
     d.partial_begin = floats;
-    items += (int64_t)d.n_bgroups * d.n_cw;
+    items += d.n_witems;
     pairs += d.n_frames - 1;
     floats += (int64_t)(d.n_frames - 1) * levels * d.n_witems * 10;
   }
@@ -525,7 +530,7 @@ extern "C" int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_
   f.table = nullptr;
   f.n_seqs = 1;
   f.inl = d;
-  f.n_items = (int64_t)d.n_bgroups * d.n_cw;
+  f.n_items = d.n_witems;
   f.n_pairs = 1;
   f.partials = reinterpret_cast<float*>(ws);
   f.grid = persistent_grid(f.n_items);
