@@ -215,6 +215,23 @@ typedef struct tc_ttc_plan tc_ttc_plan;
  * level l is levels_out[pair_base(s) * L + p * L + l] and picks_out[pair_base(s) + p],
  * pair_base(s) = sum over earlier streams of (n_frames - 1). */
 int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan);
+
+/* Launch shape of the fused pass.  band_rows: base rows owned by one wave
+ * (8, 16 or 32; taller bands walk fewer halo rows per owned row but need more
+ * LDS per wave); groups_per_cu: work-groups (one wave each) of the persistent
+ * grid per compute unit (1..64).  The sums depend on band_rows through their
+ * blocking (not on groups_per_cu); a fixed tuning gives bit-identical results
+ * for a stream whatever else is in the batch. */
+typedef struct {
+  int32_t band_rows;
+  int32_t groups_per_cu;
+} tc_ttc_tuning;
+/* The built-in tuning for (dtype, levels), chosen by the tuning sweep of the
+ * fused pass on MI355X. */
+int tc_ttc_tuning_default(int32_t dtype, int32_t levels, tc_ttc_tuning* out);
+/* tc_ttc_plan_create with an explicit tuning (NULL = the built-in one). */
+int tc_ttc_plan_create_ex(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, const tc_ttc_tuning* tuning,
+                          tc_ttc_plan** plan);
 /* Workspace bytes the plan needs, the total number of pairs and the number
  * of tc_ttc_level records (pairs * levels). */
 int tc_ttc_plan_info(const tc_ttc_plan* plan, size_t* ws_bytes, int64_t* n_pairs, int64_t* n_level_records);

@@ -35,6 +35,10 @@ class TcTensor(C.Structure):
     ]
 
 
+class TcTuning(C.Structure):
+    _fields_ = [("band_rows", C.c_int32), ("groups_per_cu", C.c_int32)]
+
+
 class TcSeq(C.Structure):
     _fields_ = [
         ("frame0", C.c_void_p),
@@ -76,6 +80,8 @@ SIGNATURES = {
     "tc_image_pyramid": (_I, [_T, _I32, _T, _P]),
     "tc_horn_derivs": (_I, [_T, _T, _T, _T, _T, _P]),
     "tc_ttc_plan_create": (_I, [C.POINTER(TcSeq), _I32, _I32, C.POINTER(_P)]),
+    "tc_ttc_tuning_default": (_I, [_I32, _I32, C.POINTER(TcTuning)]),
+    "tc_ttc_plan_create_ex": (_I, [C.POINTER(TcSeq), _I32, _I32, C.POINTER(TcTuning), C.POINTER(_P)]),
     "tc_ttc_plan_info": (_I, [_P, C.POINTER(_SZ), C.POINTER(_I64), C.POINTER(_I64)]),
     "tc_ttc_plan_upload": (_I, [_P, _P, _SZ, _P]),
     "tc_ttc_plan_run": (_I, [_P, _P, _SZ, _P, _P, _P]),

@@ -174,12 +174,19 @@ def seq_from_pair(prev: torch.Tensor, nxt: torch.Tensor, levels: int) -> L.TcSeq
 class TTCPlan:
     """A batch of streams planned once and run many times (graph-capturable run)."""
 
-    def __init__(self, seqs: Sequence[L.TcSeq], dtype: torch.dtype, device=None, keep: Sequence = ()):
+    def __init__(self, seqs: Sequence[L.TcSeq], dtype: torch.dtype, device=None, keep: Sequence = (),
+                 tuning: Optional[Tuple[int, int]] = None):
         self._lib = _lib()
         self._keep = list(keep)  # tensors the descriptors point into
         arr = (L.TcSeq * len(seqs))(*seqs)
         h = C.c_void_p()
-        L.check("tc_ttc_plan_create", self._lib.tc_ttc_plan_create(arr, len(seqs), _DT[dtype], C.byref(h)))
+        tn = None
+        if tuning is not None:
+            tn = L.TcTuning()
+            tn.band_rows, tn.groups_per_cu = int(tuning[0]), int(tuning[1])
+        L.check("tc_ttc_plan_create_ex",
+                self._lib.tc_ttc_plan_create_ex(arr, len(seqs), _DT[dtype], C.byref(tn) if tn is not None else None,
+                                                C.byref(h)))
         self._h = h
         ws = C.c_size_t(0)
         npairs = C.c_int64(0)
@@ -231,10 +238,17 @@ class TTCPlan:
             pass
 
 
-def ttc_solve_batched(videos: Sequence[torch.Tensor], levels: int, stream=None):
+def tuning_default(dtype: torch.dtype, levels: int) -> Tuple[int, int]:
+    """The library's built-in (band_rows, groups_per_cu) for a dtype and level count."""
+    t = L.TcTuning()
+    L.check("tc_ttc_tuning_default", _lib().tc_ttc_tuning_default(_DT[dtype], levels, C.byref(t)))
+    return t.band_rows, t.groups_per_cu
+
+
+def ttc_solve_batched(videos: Sequence[torch.Tensor], levels: int, stream=None, tuning=None):
     """Every consecutive pair of every [F, H, W] video -> (levels records, picks) as numpy arrays."""
     dtype = videos[0].dtype
-    plan = TTCPlan([seq_from_frames(v, levels) for v in videos], dtype, videos[0].device, keep=videos)
+    plan = TTCPlan([seq_from_frames(v, levels) for v in videos], dtype, videos[0].device, keep=videos, tuning=tuning)
     plan.run(stream)
     torch.cuda.synchronize()
     out = plan.results()

@@ -1,0 +1,100 @@
+"""Tuning sweep of the fused TTC pass.
+
+For a (dtype, levels) class the sweep times the fused kernel over a
+representative batch for every candidate launch shape -- band height (rows a
+wave owns: 8, 16, 32) and persistent work-groups per compute unit -- with HIP
+events on the launch stream, and keeps the fastest.  Candidates that fail to
+create a plan are skipped.  The table it prints is what the library's built-in
+default (``tc_ttc_tuning_default``) is set from; callers can also pass a tuning
+to ``TTCPlan(..., tuning=(band_rows, groups_per_cu))``.
+
+    python -m paper_1612_08825_amd.autotune [--out table.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+from typing import Dict, List, Sequence, Tuple
+
+BAND_ROWS = (8, 16, 32)
+GROUPS_PER_CU = (8, 16, 32, 64)
+
+
+def time_plan(api, torch, videos, levels: int, tuning: Tuple[int, int], reps: int, warmup: int) -> float:
+    """Average fused-pass milliseconds for one launch shape."""
+    plan = api.TTCPlan([api.seq_from_frames(v, levels) for v in videos], videos[0].dtype, keep=videos, tuning=tuning)
+    try:
+        plan.upload()
+        for _ in range(warmup):
+            plan.run_phase(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.run_phase(1)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    finally:
+        plan.close()
+
+
+def sweep(videos, levels: int, band_rows: Sequence[int] = BAND_ROWS, groups: Sequence[int] = GROUPS_PER_CU,
+          reps: int = 10, warmup: int = 2) -> List[Dict]:
+    import torch
+
+    from . import api
+
+    rows = []
+    for rh in band_rows:
+        for gpc in groups:
+            try:
+                ms = time_plan(api, torch, videos, levels, (rh, gpc), reps, warmup)
+            except Exception as exc:  # a shape this build does not provide
+                rows.append({"band_rows": rh, "groups_per_cu": gpc, "ms": None, "error": str(exc)})
+                continue
+            rows.append({"band_rows": rh, "groups_per_cu": gpc, "ms": round(ms, 4)})
+            print(f"[tune] rows={rh:2d} groups/CU={gpc:2d}: {ms:.4f} ms", file=sys.stderr, flush=True)
+    return rows
+
+
+def best(rows: List[Dict]) -> Dict:
+    ok = [r for r in rows if r.get("ms") is not None]
+    return min(ok, key=lambda r: r["ms"])
+
+
+def workloads(torch):
+    """Representative batches: the batched f16 workload (4 levels) and a u8
+    mix like the serving streams (3 levels)."""
+    from . import synth
+
+    f16 = [s.render(device="cuda") for s in synth.batched_specs()]
+    u8 = [s.render(device="cuda") for s in synth.serving_specs(n_streams=64)]
+    torch.cuda.synchronize()
+    return {("f16", 4): f16, ("u8", 3): u8}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--reps", type=int, default=10)
+    args = ap.parse_args()
+    import torch
+
+    table = {}
+    for (dt, levels), vids in workloads(torch).items():
+        rows = sweep(vids, levels, reps=args.reps)
+        b = best(rows)
+        table[f"{dt}/L{levels}"] = {"best": {"band_rows": b["band_rows"], "groups_per_cu": b["groups_per_cu"],
+                                             "ms": b["ms"]}, "sweep": rows}
+        del vids
+        torch.cuda.empty_cache()
+    text = json.dumps(table, indent=1)
+    print(text)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+
+
+if __name__ == "__main__":
+    main()

@@ -294,15 +294,21 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Band height per (dtype, levels): the rows a wave owns.  Chosen by the tuning
-// sweep of the fused pass; a multiple of 2^(levels-1) for every entry.
-int choose_band_rows(int dtype, int levels) {
+// Built-in launch shape per (dtype, levels), from the tuning sweep of the fused
+// pass (paper_1612_08825_amd/autotune.py) on MI355X.
+// Sweep on MI355X (fused-pass ms; batched f16 workload at 4 levels, 64-stream
+// u8 mix at 3 levels): f16 best at 8 rows x 32 groups/CU (1.122 ms; 16 rows:
+// 1.298, 32 rows: 1.767), u8 best at 16 rows x 32 groups/CU (0.884 ms).
+tc_ttc_tuning default_tuning(int dtype, int levels) {
   (void)levels;
-  if (const char* e = getenv("TC_BAND_ROWS")) {
-    const int v = atoi(e);
-    if (v == 8 || v == 16 || v == 32) return v;
-  }
-  return dtype == TC_U8 ? 16 : 8;
+  tc_ttc_tuning t;
+  t.band_rows = dtype == TC_U8 ? 16 : 8;
+  t.groups_per_cu = 32;
+  return t;
+}
+
+bool tuning_ok(const tc_ttc_tuning& t, int dtype, int levels) {
+  return t.groups_per_cu >= 1 && t.groups_per_cu <= 64 && fused_variant_exists(dtype, levels, t.band_rows);
 }
 
 int validate_seq(const tc_seq& q, int dtype, int levels) {
@@ -343,16 +349,24 @@ void fill_desc(SeqDesc& d, const tc_seq& q, int dtype, int band_rows) {
   d.vec = vector_ok(q, dtype);
 }
 
-int persistent_grid(int64_t n_items) {
+int persistent_grid(int64_t n_items, int groups_per_cu) {
   const int n_cu = current_cu_count();
-  int64_t g = std::min<int64_t>(n_items, (int64_t)n_cu * 16);
+  int64_t g = std::min<int64_t>(n_items, (int64_t)n_cu * groups_per_cu);
   if (g >= 8) g -= g % 8;
   return (int)std::max<int64_t>(g, 1);
 }
 
 }  // namespace
 
-extern "C" int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan) {
+extern "C" int tc_ttc_tuning_default(int32_t dtype, int32_t levels, tc_ttc_tuning* out) {
+  if (!out || levels < 1 || levels > TC_MAX_LEVELS) return TC_EINVAL;
+  if (dtype != TC_U8 && dtype != TC_F16) return TC_EDTYPE;
+  *out = default_tuning(dtype, levels);
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_plan_create_ex(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, const tc_ttc_tuning* tuning,
+                                     tc_ttc_plan** plan) {
   if (!plan) return TC_EINVAL;
   *plan = nullptr;
   if (!seqs || n_seqs < 1 || n_seqs > (1 << 20)) return TC_EINVAL;
@@ -363,8 +377,9 @@ extern "C" int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dt
     const int st = validate_seq(seqs[i], dtype, levels);
     if (st != TC_OK) return st;
   }
-  const int rh = choose_band_rows(dtype, levels);
-  if (!fused_variant_exists(dtype, levels, rh)) return TC_EINVAL;
+  const tc_ttc_tuning tn = tuning ? *tuning : default_tuning(dtype, levels);
+  if (!tuning_ok(tn, dtype, levels)) return TC_EINVAL;
+  const int rh = tn.band_rows;
 
   tc_ttc_plan* p = new (std::nothrow) tc_ttc_plan();
   if (!p) return TC_ENOMEM;
@@ -393,9 +408,13 @@ extern "C" int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dt
   p->n_pairs = pairs;
   p->n_partial_floats = floats;
   p->ws_bytes = p->table_bytes + align_up((size_t)floats * sizeof(float));
-  p->grid = persistent_grid(items);
+  p->grid = persistent_grid(items, tn.groups_per_cu);
   *plan = p;
   return TC_OK;
+}
+
+extern "C" int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan) {
+  return tc_ttc_plan_create_ex(seqs, n_seqs, dtype, nullptr, plan);
 }
 
 extern "C" int tc_ttc_plan_info(const tc_ttc_plan* plan, size_t* ws_bytes, int64_t* n_pairs,
@@ -486,7 +505,7 @@ int pair_desc(const tc_tensor* prev, const tc_tensor* next, int32_t levels, SeqD
   q.n_frames = 2;
   q.levels = levels;
   if ((st = validate_seq(q, prev->dtype, levels)) != TC_OK) return st;
-  fill_desc(d, q, prev->dtype, choose_band_rows(prev->dtype, levels));
+  fill_desc(d, q, prev->dtype, default_tuning(prev->dtype, levels).band_rows);
   d.item_begin = 0;
   d.pair_begin = 0;
   d.partial_begin = 0;
@@ -509,7 +528,7 @@ extern "C" int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_
     q.n_frames = 2;
     q.levels = levels;
     SeqDesc d{};
-    fill_desc(d, q, dt, choose_band_rows(dt, levels));
+    fill_desc(d, q, dt, 8);  // the smallest band height has the most partials
     best = std::max(best, pair_ws_bytes(d));
   }
   *ws_bytes = best;
@@ -533,7 +552,7 @@ extern "C" int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_
   f.n_items = d.n_witems;
   f.n_pairs = 1;
   f.partials = reinterpret_cast<float*>(ws);
-  f.grid = persistent_grid(f.n_items);
+  f.grid = persistent_grid(f.n_items, default_tuning(prev->dtype, levels).groups_per_cu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (launch_ttc_fused(f, s) != hipSuccess) return TC_EDEVICE;
   if (launch_ttc_finish(f, levels_out, pick_out, s) != hipSuccess) return TC_EDEVICE;
