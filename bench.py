@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-conv", action="store_true")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg, no conv sweep (for rocprofv3)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="measured serving time after 1 s of warm-up")
+    ap.add_argument("--serve-rate", type=float, default=20000.0, help="aggregate frame arrivals per second")
+    ap.add_argument("--serve-budget-gib", type=float, default=2.0, help="device memory for stream state")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--save-frames", default=None, help="render the batch, save it to this .npz and exit")
     ap.add_argument("--load-frames", default=None, help="take the batch from a .npz written by --save-frames")
     return ap.parse_args()
@@ -148,6 +153,113 @@ def conv_sweep(api, torch, steps):
         del xbufs, ybufs
         torch.cuda.empty_cache()
     return out
+
+
+# ----------------------------------------------------------------------------- plain path
+def plain_path(api, torch, vids, reps=3):
+    """The same pairs, one tc_ttc_solve call (fused + finishing launch) per pair,
+    workspace and outputs allocated once; wall time over the whole batch."""
+    levels_rec = []
+    H = max(int(v.shape[1]) for v in vids)
+    W = max(int(v.shape[2]) for v in vids)
+    ws = torch.empty(api.ttc_workspace_size(H, W, LEVELS), dtype=torch.uint8, device="cuda")
+    n_pairs = sum(int(v.shape[0]) - 1 for v in vids)
+    lv = torch.empty(n_pairs * LEVELS * 152, dtype=torch.uint8, device="cuda")
+    pk = torch.empty(n_pairs * 56, dtype=torch.uint8, device="cuda")
+
+    def one_pass():
+        q = 0
+        for v in vids:
+            for t in range(int(v.shape[0]) - 1):
+                api.ttc_solve(v[t], v[t + 1], LEVELS, ws=ws,
+                              out=(lv[q * LEVELS * 152:(q + 1) * LEVELS * 152], pk[q * 56:(q + 1) * 56]))
+                q += 1
+
+    one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one_pass()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return ms, lv, pk
+
+
+# ----------------------------------------------------------------------------- serving
+def serving_bench(api, torch, args):
+    """Open-loop serving of 256 u8 camera streams (3 levels) at a fixed Poisson
+    load: continuous batching, stream state admitted by device-memory budget."""
+    import numpy as np
+
+    from paper_1612_08825_amd import serving as S
+    from paper_1612_08825_amd import synth
+
+    specs = synth.serving_specs()
+    levels = 3
+    # every stream's 16 frames in one pinned host buffer (the cameras' frames)
+    sizes = [s.n_frames * s.H * s.W for s in specs]
+    pinned = torch.empty(sum(sizes), dtype=torch.uint8, pin_memory=True)
+    host = []
+    off = 0
+    for s, n in zip(specs, sizes):
+        v = pinned[off:off + n].view(s.n_frames, s.H, s.W)
+        v.copy_(s.render(device="cuda"))
+        host.append(v)
+        off += n
+    torch.cuda.synchronize()
+    warm = 1.0
+    times, ids = synth.poisson_arrivals(args.serve_rate, warm + args.serve_seconds, len(specs))
+    budget = int(args.serve_budget_gib * 2 ** 30)
+    sched = S.Scheduler([(s.H, s.W) for s in specs], budget)
+    ex = S.GpuExecutor(host, levels=levels, max_inflight=2)
+    print(f"[bench] serving {times.size} requests over {warm + args.serve_seconds:.0f} s", file=sys.stderr, flush=True)
+    st = S.run_open_loop(sched, ex, times, ids, max_inflight=2)
+    torch.cuda.synchronize()
+    reqs = st.requests
+    lat = S.latency_summary(reqs, t_from=warm)
+    measured = [r for r in reqs if r.t_arrival >= warm]
+    pairs = [r for r in measured if r.kind == S.PAIR]
+    px = sum(specs[r.stream].H * specs[r.stream].W for r in pairs)
+    t_end = max(r.t_done for r in measured)
+    span = t_end - warm
+    ok = [r for r in pairs if r.status == 0]
+    # ground truth holds for pairs that do not wrap from the last rendered frame to the first
+    nowrap = [r for r in ok if r.k % specs[r.stream].n_frames != 0]
+    rel = [abs(r.pick["ttc"] - specs[r.stream].ttc) / specs[r.stream].ttc for r in nowrap]
+
+    # a sample of served pairs solved again, each alone in its own plan: bitwise equal
+    rng = np.random.default_rng(5)
+    sample = [pairs[i] for i in rng.choice(len(pairs), size=min(32, len(pairs)), replace=False)]
+    equal = True
+    for r in sample:
+        fr = host[r.stream]
+        F = fr.shape[0]
+        pair = torch.stack([fr[(r.k - 1) % F], fr[r.k % F]]).cuda()
+        lv, pk = api.ttc_solve_batched([pair], levels)
+        equal &= pk[0].tobytes() == r.pick.tobytes() and lv.tobytes() == r.levels.tobytes()
+    mean_px = float(np.mean([s.H * s.W for s in specs]))
+    return {
+        "workload": "256 u8 camera streams of mixed sizes (320x240..1920x1080), frame-pair requests arriving "
+                    f"Poisson at {args.serve_rate:.0f}/s, 3-level pyramid, per-stream state resident on the device",
+        "requests": len(measured),
+        "pairs_answered": len(pairs),
+        "offered_Gpixel_per_s": round(args.serve_rate * mean_px / 1e9, 3),
+        "served_Gpixel_per_s": round(px / span / 1e9, 3),
+        "latency_ms": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in lat.items()},
+        "batches": st.batches,
+        "mean_batch": round(float(np.mean(st.batch_sizes)), 2),
+        "max_batch": int(max(st.batch_sizes)),
+        "budget_bytes": budget,
+        "peak_state_bytes": sched.peak_bytes,
+        "admissions": sched.admissions,
+        "evictions": sched.evictions,
+        "ok_status_frac": round(len(ok) / max(1, len(pairs)), 4),
+        "median_rel_err_vs_ground_truth": float(np.median(rel)) if rel else None,
+        "sample_alone_equals_mix": bool(equal),
+        "sample_size": len(sample),
+        "warmup_s": warm,
+        "measured_s": round(span, 3),
+    }
 
 
 # ----------------------------------------------------------------------------- main
@@ -281,14 +393,40 @@ def main():
         roof = {"bound": "hbm", "achieved": round(ach_gb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach_gb / HBM_PEAK_GBPS, 4)}
     roof["traffic"] = None
-    roof["kernel"] = "ttc_fused<_Float16, 4, 8>"
+    rh, gpc = api.tuning_default(torch.float16, LEVELS)
+    roof["kernel"] = f"ttc_fused<_Float16, {LEVELS}, {rh}>"
+    roof["launch"] = {"band_rows": rh, "groups_per_cu": gpc}
     roof["kernel_ms"] = round(fused_avg, 4)
     roof["alg_bytes"] = alg_bytes
     roof["alg_flops"] = flops
 
+    plain = None
+    if not args.no_plain and not args.profile:
+        plain_ms, plain_lv, plain_pk = plain_path(api, torch, vids)
+        # the same pairs through the batched plan: equal accuracy means equal results
+        ppk = api.decode_picks(plain_pk)
+        bpk = api.decode_picks(plan.picks_buf[: plan.n_pairs * 56])
+        both = (ppk["status"] == 0) & (bpk["status"] == 0)
+        plain = {"ms_per_step": round(plain_ms, 3), "Gpixel_per_s": round(pair_px / (plain_ms * 1e-3) / 1e9, 3),
+                 "launches_per_step": 2 * int(plan.n_pairs),
+                 "picks_bitwise_equal_batched": bool(ppk.tobytes() == bpk.tobytes()),
+                 "max_rel_ttc_diff_vs_batched": float(np.max(np.abs(ppk["ttc"][both] - bpk["ttc"][both])
+                                                             / np.abs(bpk["ttc"][both]))) if both.any() else None}
+        del plain_lv, plain_pk
+        print(f"[bench] plain path done: {plain['Gpixel_per_s']} Gpixel/s", file=sys.stderr, flush=True)
+
     conv = None
     if not args.no_conv:
         conv = conv_sweep(api, torch, max(10, args.steps))
+        print("[bench] conv sweep done", file=sys.stderr, flush=True)
+
+    serve = None
+    if not args.no_serve and not args.profile:
+        del vids
+        plan.close()
+        torch.cuda.empty_cache()
+        serve = serving_bench(api, torch, args)
+        print(f"[bench] serving done: p50 {serve['latency_ms'].get('p50_ms')} ms", file=sys.stderr, flush=True)
 
     value = pair_px / (ms_per_step * 1e-3) / 1e9
     line = {
@@ -325,6 +463,8 @@ def main():
         "deterministic_across_steps": deterministic,
         "accuracy": {"ok_status_frac": ok_frac, "median_rel_err_vs_ground_truth": float(np.median(rel_err_sel))},
         "cpu_baseline": cpu,
+        "plain_one_pair_per_launch": plain,
+        "serving": serve,
         "conv_sweep": conv,
         "device": {"cus": n_cu, "name": torch.cuda.get_device_name(0)},
     }

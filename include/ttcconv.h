@@ -232,6 +232,12 @@ int tc_ttc_tuning_default(int32_t dtype, int32_t levels, tc_ttc_tuning* out);
 /* tc_ttc_plan_create with an explicit tuning (NULL = the built-in one). */
 int tc_ttc_plan_create_ex(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, const tc_ttc_tuning* tuning,
                           tc_ttc_plan** plan);
+/* Re-plans an existing plan for a new batch (same dtype and levels) in place:
+ * the pinned table is reused when it is large enough (re-allocated otherwise).
+ * For serving loops that plan every tick.  The plan's previous upload must
+ * have completed (the table is overwritten), and the workspace size may change
+ * (query it again with tc_ttc_plan_info). */
+int tc_ttc_plan_reset(tc_ttc_plan* plan, const tc_seq* seqs, int32_t n_seqs);
 /* Workspace bytes the plan needs, the total number of pairs and the number
  * of tc_ttc_level records (pairs * levels). */
 int tc_ttc_plan_info(const tc_ttc_plan* plan, size_t* ws_bytes, int64_t* n_pairs, int64_t* n_level_records);

@@ -82,6 +82,7 @@ SIGNATURES = {
     "tc_ttc_plan_create": (_I, [C.POINTER(TcSeq), _I32, _I32, C.POINTER(_P)]),
     "tc_ttc_tuning_default": (_I, [_I32, _I32, C.POINTER(TcTuning)]),
     "tc_ttc_plan_create_ex": (_I, [C.POINTER(TcSeq), _I32, _I32, C.POINTER(TcTuning), C.POINTER(_P)]),
+    "tc_ttc_plan_reset": (_I, [_P, C.POINTER(TcSeq), _I32]),
     "tc_ttc_plan_info": (_I, [_P, C.POINTER(_SZ), C.POINTER(_I64), C.POINTER(_I64)]),
     "tc_ttc_plan_upload": (_I, [_P, _P, _SZ, _P]),
     "tc_ttc_plan_run": (_I, [_P, _P, _SZ, _P, _P, _P]),

@@ -188,18 +188,35 @@ class TTCPlan:
                 self._lib.tc_ttc_plan_create_ex(arr, len(seqs), _DT[dtype], C.byref(tn) if tn is not None else None,
                                                 C.byref(h)))
         self._h = h
+        self._dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws = self.levels_buf = self.picks_buf = None
+        self._size_buffers()
+
+    def _size_buffers(self):
         ws = C.c_size_t(0)
         npairs = C.c_int64(0)
         nrec = C.c_int64(0)
-        L.check("tc_ttc_plan_info", self._lib.tc_ttc_plan_info(h, C.byref(ws), C.byref(npairs), C.byref(nrec)))
+        L.check("tc_ttc_plan_info", self._lib.tc_ttc_plan_info(self._h, C.byref(ws), C.byref(npairs), C.byref(nrec)))
         self.ws_bytes = ws.value
         self.n_pairs = npairs.value
         self.n_records = nrec.value
-        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.ws = torch.empty(max(1, self.ws_bytes), dtype=torch.uint8, device=dev)
-        self.levels_buf = torch.empty(max(1, self.n_records) * L.LEVEL_DTYPE.itemsize, dtype=torch.uint8, device=dev)
-        self.picks_buf = torch.empty(max(1, self.n_pairs) * L.PICK_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        need = (max(1, self.ws_bytes), max(1, self.n_records) * L.LEVEL_DTYPE.itemsize,
+                max(1, self.n_pairs) * L.PICK_DTYPE.itemsize)
+        if self.ws is None or self.ws.numel() < need[0]:
+            self.ws = torch.empty(need[0], dtype=torch.uint8, device=self._dev)
+        if self.levels_buf is None or self.levels_buf.numel() < need[1]:
+            self.levels_buf = torch.empty(need[1], dtype=torch.uint8, device=self._dev)
+        if self.picks_buf is None or self.picks_buf.numel() < need[2]:
+            self.picks_buf = torch.empty(need[2], dtype=torch.uint8, device=self._dev)
         self.uploaded = False
+
+    def reset(self, seqs: Sequence[L.TcSeq], keep: Sequence = ()):
+        """Re-plan for a new batch with the same dtype and levels.  The previous
+        upload must have completed; buffers grow when the new batch needs more."""
+        arr = (L.TcSeq * len(seqs))(*seqs)
+        L.check("tc_ttc_plan_reset", self._lib.tc_ttc_plan_reset(self._h, arr, len(seqs)))
+        self._keep = list(keep)
+        self._size_buffers()
 
     def upload(self, stream=None):
         L.check("tc_ttc_plan_upload", self._lib.tc_ttc_plan_upload(self._h, C.c_void_p(self.ws.data_ptr()),

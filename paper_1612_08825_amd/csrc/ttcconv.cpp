@@ -279,6 +279,8 @@ struct tc_ttc_plan {
   int dtype = 0;
   int levels = 0;
   int band_rows = 0;
+  int groups_per_cu = 0;
+  int capacity = 0;  // table entries the pinned buffer holds
   int n_seqs = 0;
   int64_t n_items = 0;
   int64_t n_pairs = 0;
@@ -358,6 +360,50 @@ int persistent_grid(int64_t n_items, int groups_per_cu) {
 
 }  // namespace
 
+// (Re)builds the plan's work table for `seqs` in its pinned buffer.
+static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
+  if (n_seqs > p->capacity) {
+    if (p->table) (void)hipHostFree(p->table);
+    p->table = nullptr;
+    p->capacity = 0;
+    const size_t bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->table), bytes, hipHostMallocDefault) != hipSuccess) {
+      p->table = nullptr;
+      return TC_EDEVICE;
+    }
+    p->capacity = n_seqs;
+  }
+  p->n_seqs = n_seqs;
+  p->table_bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
+  memset(p->table, 0, sizeof(SeqDesc) * (size_t)n_seqs);
+  int64_t items = 0, pairs = 0, floats = 0;
+  for (int i = 0; i < n_seqs; ++i) {
+    SeqDesc& d = p->table[i];
+    fill_desc(d, seqs[i], p->dtype, p->band_rows);
+    d.item_begin = items;
+    d.pair_begin = pairs;
+    d.partial_begin = floats;
+    items += d.n_witems;
+    pairs += d.n_frames - 1;
+    floats += (int64_t)(d.n_frames - 1) * p->levels * d.n_witems * 10;
+  }
+  p->n_items = items;
+  p->n_pairs = pairs;
+  p->n_partial_floats = floats;
+  p->ws_bytes = p->table_bytes + align_up((size_t)floats * sizeof(float));
+  p->grid = persistent_grid(items, p->groups_per_cu);
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_plan_reset(tc_ttc_plan* plan, const tc_seq* seqs, int32_t n_seqs) {
+  if (!plan || !seqs || n_seqs < 1 || n_seqs > (1 << 20)) return TC_EINVAL;
+  for (int i = 0; i < n_seqs; ++i) {
+    const int st = validate_seq(seqs[i], plan->dtype, plan->levels);
+    if (st != TC_OK) return st;
+  }
+  return plan_fill(plan, seqs, n_seqs);
+}
+
 extern "C" int tc_ttc_tuning_default(int32_t dtype, int32_t levels, tc_ttc_tuning* out) {
   if (!out || levels < 1 || levels > TC_MAX_LEVELS) return TC_EINVAL;
   if (dtype != TC_U8 && dtype != TC_F16) return TC_EDTYPE;
@@ -386,29 +432,12 @@ extern "C" int tc_ttc_plan_create_ex(const tc_seq* seqs, int32_t n_seqs, int32_t
   p->dtype = dtype;
   p->levels = levels;
   p->band_rows = rh;
-  p->n_seqs = n_seqs;
-  p->table_bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
-  if (hipHostMalloc(reinterpret_cast<void**>(&p->table), p->table_bytes, hipHostMallocDefault) != hipSuccess) {
-    delete p;
-    return TC_EDEVICE;
+  p->groups_per_cu = tn.groups_per_cu;
+  const int st = plan_fill(p, seqs, n_seqs);
+  if (st != TC_OK) {
+    tc_ttc_plan_destroy(p);
+    return st;
   }
-  memset(p->table, 0, p->table_bytes);
-  int64_t items = 0, pairs = 0, floats = 0;
-  for (int i = 0; i < n_seqs; ++i) {
-    SeqDesc& d = p->table[i];
-    fill_desc(d, seqs[i], dtype, rh);
-    d.item_begin = items;
-    d.pair_begin = pairs;
-    d.partial_begin = floats;
-    items += d.n_witems;
-    pairs += d.n_frames - 1;
-    floats += (int64_t)(d.n_frames - 1) * levels * d.n_witems * 10;
-  }
-  p->n_items = items;
-  p->n_pairs = pairs;
-  p->n_partial_floats = floats;
-  p->ws_bytes = p->table_bytes + align_up((size_t)floats * sizeof(float));
-  p->grid = persistent_grid(items, tn.groups_per_cu);
   *plan = p;
   return TC_OK;
 }
