@@ -19,6 +19,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -49,6 +50,32 @@ def parse():
     ap.add_argument("--save-frames", default=None, help="render the batch, save it to this .npz and exit")
     ap.add_argument("--load-frames", default=None, help="take the batch from a .npz written by --save-frames")
     return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------- measured traffic
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttc_fused_batched64_f16_L4.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_08825_amd", "csrc", f)
+                  for f in ("ttc.hip", "device_common.hpp", "internal.hpp")]
+
+
+def profiled_traffic():
+    """HBM bytes per fused launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, calibrated against a copy of known size), or None when the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^(kernel_source_sha256|traffic_bytes_per_launch) = (\S+)$", text, flags=re.M))
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    if vals.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return int(vals["traffic_bytes_per_launch"])
 
 
 # ----------------------------------------------------------------------------- algorithmic work
@@ -392,7 +419,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(ach_gb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(ach_gb / HBM_PEAK_GBPS, 4)}
-    roof["traffic"] = None
+    roof["traffic"] = profiled_traffic()
     rh, gpc = api.tuning_default(torch.float16, LEVELS)
     roof["kernel"] = f"ttc_fused<_Float16, {LEVELS}, {rh}>"
     roof["launch"] = {"band_rows": rh, "groups_per_cu": gpc}

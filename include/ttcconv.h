@@ -219,7 +219,7 @@ int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc
 /* Launch shape of the fused pass.  band_rows: base rows owned by one wave
  * (8, 16 or 32; taller bands walk fewer halo rows per owned row but need more
  * LDS per wave); groups_per_cu: work-groups (one wave each) of the persistent
- * grid per compute unit (1..64).  The sums depend on band_rows through their
+ * grid per compute unit (1..256).  The sums depend on band_rows through their
  * blocking (not on groups_per_cu); a fixed tuning gives bit-identical results
  * for a stream whatever else is in the batch. */
 typedef struct {

@@ -18,7 +18,7 @@ import sys
 from typing import Dict, List, Sequence, Tuple
 
 BAND_ROWS = (8, 16, 32)
-GROUPS_PER_CU = (8, 16, 32, 64)
+GROUPS_PER_CU = (8, 16, 32, 64, 128)
 
 
 def time_plan(api, torch, videos, levels: int, tuning: Tuple[int, int], reps: int, warmup: int) -> float:

@@ -56,6 +56,18 @@ template <> struct Raw8<uint8_t> {
 #pragma unroll
     for (int c = 0; c < 8; ++c) f[c] = (float)((d[c >> 2] >> (8 * (c & 3))) & 0xffu);
   }
+  // Temporal sum and difference with the same pixels of the previous frame:
+  // S = old + this, D = this - old, in FP32 (exact: integers below 2^9).
+  __device__ __forceinline__ void sum_diff(const Raw8& old, float (&S)[8], float (&D)[8]) const {
+    float a[8], b[8];
+    old.unpack(a);
+    unpack(b);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      S[c] = a[c] + b[c];
+      D[c] = b[c] - a[c];
+    }
+  }
 };
 
 template <> struct Raw8<_Float16> {
@@ -82,6 +94,37 @@ template <> struct Raw8<_Float16> {
     for (int c = 0; c < 8; ++c) {
       const uint16_t h = (uint16_t)((d[c >> 1] >> (16 * (c & 1))) & 0xffffu);
       f[c] = (float)__builtin_bit_cast(_Float16, h);
+    }
+  }
+  // Temporal sum and difference with the same pixels of the previous frame:
+  // S = old + this, D = this - old, in FP32 with one rounding each.
+  //
+  // v_fma_mix_f32 converts its f16 operands (either half of a dword, chosen by
+  // op_sel) to FP32 exactly and computes a * 1.0 + c with a single rounding, so
+  // one instruction gives what a conversion of each operand and an FP32 add
+  // give in three.  The compiler does not form it by itself here.
+  //
+  // Column 0 is computed in plain code: its S and D are the ones a DPP move
+  // reads next (the right neighbour of the lane to the left), and the hazard
+  // check that spaces a VALU write from a DPP read of the same register does
+  // not see writes made inside inline assembly.
+  __device__ __forceinline__ void sum_diff(const Raw8& old, float (&S)[8], float (&D)[8]) const {
+    {
+      const float a = (float)__builtin_bit_cast(_Float16, (uint16_t)(old.d[0] & 0xffffu));
+      const float b = (float)__builtin_bit_cast(_Float16, (uint16_t)(d[0] & 0xffffu));
+      S[0] = a + b;
+      D[0] = b - a;
+    }
+    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(S[1]) : "v"(d[0]), "v"(old.d[0]));
+    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(D[1]) : "v"(d[0]), "v"(old.d[0]));
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+      asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(S[2 * i]) : "v"(d[i]), "v"(old.d[i]));
+      asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(D[2 * i]) : "v"(d[i]), "v"(old.d[i]));
+      asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(S[2 * i + 1]) : "v"(d[i]),
+          "v"(old.d[i]));
+      asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(D[2 * i + 1]) : "v"(d[i]),
+          "v"(old.d[i]));
     }
   }
 };

@@ -15,7 +15,7 @@
 //     stays in LDS in its packed u8 / f16 form (each lane reads and writes only
 //     its own slots), so every frame is read from memory once; each new frame
 //     row is combined with the stored one as the temporal sum S = P0 + P1 and
-//     difference D = P1 - P0.  The current frame's rows are prefetched a few
+//     difference D = P1 - P0 (for f16 frames one mixed-precision FMA each).  The current frame's rows are prefetched a few
 //     rows ahead into registers.
 //   * Rows are walked top to bottom.  Horizontal neighbour sums/differences of
 //     S and D give the derivative cube by one more vertical step.  Because the
@@ -25,8 +25,9 @@
 //     un-normalised block sums; the powers of two are removed in FP64 at the end.
 //   * The walk continues 2^(LV-1) rows past the band (halo) so that the last
 //     owned cube row of every level has its lower neighbour.
-//   * Per pair each lane sums its cubes in FP32; the wave reduces its lanes with
-//     DPP and writes one partial per (pair, level, wave).  The finishing pass
+//   * Per pair each lane sums its cubes in FP32; the wave reduces its lanes
+//     (DPP within groups of 8 lanes, then the 8 group totals through LDS) and
+//     writes one partial per (pair, level, wave).  The finishing pass
 //     combines the partials of a pair in a fixed order with TwoSum (hi, lo)
 //     compensation, converts to FP64, solves and selects the level.
 //
@@ -172,17 +173,6 @@ __device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&
   }
 }
 
-// Sum over all 64 lanes, delivered to the lanes of the last 16-lane row
-// (lanes 48..63): a DPP butterfly inside each row, then the row totals are
-// chained with row_bcast15 (row r+1 += last lane of row r, rows 1 and 3) and
-// row_bcast31 (rows 2, 3 += lane 31).
-__device__ __forceinline__ float wave_total_row3(float v) {
-  v = row16_allreduce(v);
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xA, 0xF, false));
-  v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xC, 0xF, false));
-  return v;
-}
-
 // The rows of a band are walked in groups of G rows (8 with four levels, so that
 // every level's row pattern repeats inside a group; 4 otherwise).  Rows walked:
 // the band plus the halo of 2^(LV-1) rows below it, rounded up to whole groups.
@@ -215,7 +205,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // rows of frame k+1 are already in flight.
 template <typename T, int LV, int RH, bool CHECK>
 __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane, int lane, float* part,
-                                          int64_t witem, Raw8<T>* prev, float* pbuf) {
+                                          int64_t witem, Raw8<T>* prev, float* pbuf, float* red) {
   constexpr int G = row_group<LV>();  // depth of the prefetch ring
   constexpr int NR = walked_rows<LV, RH>();
   const int li = lane & 15;
@@ -303,15 +293,8 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
         if (!CHECK || row0 + w < H) {
           const Raw8<T> old = prev[w * 64 + lane];
           prev[w * 64 + lane] = cur;
-          float pa[8], pb[8];
-          old.unpack(pa);
-          cur.unpack(pb);
           float S[8], D[8];
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            S[c] = pa[c] + pb[c];
-            D[c] = pb[c] - pa[c];
-          }
+          cur.sum_diff(old, S, D);
           float hs0[8], hd0[8], hD0[8];
           horizontals<8>(S, D, hs0, hd0, hD0);
           if constexpr (w >= 1 && w <= RH)
@@ -378,22 +361,44 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
       });
     }
 
-    // one partial per (pair, level, wave): lanes that own no cube of a level
-    // contribute zero; lanes 48..57 hold sum q = lane - 48.  Partials are staged
-    // in LDS and written out every kPartialChunk pairs, so that stores are
-    // rarely in flight while the next rows are being prefetched.
+    // One partial per (pair, level, wave); lanes that own no cube of a level
+    // contribute zero.  The 10 LV values are first summed over groups of 8
+    // lanes with three DPP steps, the 8 group totals pass through LDS, and lane
+    // t < 10 LV adds the 8 totals of value t (= l * 10 + q).  Partials are
+    // staged in LDS and written out every kPartialChunk pairs, so that stores
+    // are rarely in flight while the next rows are being prefetched.
     const int p = k - 1;
     const int pc = p % kPartialChunk;
+    {
+      constexpr int NV = LV * 10;
+      float v[NV];
 #pragma unroll
-    for (int l = 0; l < LV; ++l) {
-      const bool own = ncv[l] > 0;
-      float mine = 0.f;
+      for (int l = 0; l < LV; ++l) {
+        const bool own = ncv[l] > 0;
 #pragma unroll
-      for (int q = 0; q < 10; ++q) {
-        const float v = wave_total_row3(own ? acc[l][q] : 0.f);
-        mine = (lane == 48 + q) ? v : mine;
+        for (int q = 0; q < 10; ++q) v[l * 10 + q] = own ? acc[l][q] : 0.f;
       }
-      if (lane >= 48 && lane < 58) pbuf[(pc * LV + l) * 10 + (lane - 48)] = mine;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] += dpp_f32<kDppQuadXor1>(v[i]);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] += dpp_f32<kDppQuadXor2>(v[i]);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) v[i] += dpp_f32<kDppRowHalfMirror>(v[i]);
+      if ((lane & 7) == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[(lane >> 3) * NV + i] = v[i];
+      }
+      // the wave's own LDS writes above are complete before its reads below
+      // (LDS executes one wave's instructions in order); the fences only keep
+      // the compiler from moving the accesses across each other
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (lane < NV) {
+        float t = red[lane];
+#pragma unroll
+        for (int gi = 1; gi < 8; ++gi) t += red[gi * NV + lane];
+        pbuf[pc * NV + lane] = t;
+      }
     }
     if (pc == kPartialChunk - 1 || k == d.n_frames - 1) {
       __syncthreads();
@@ -419,6 +424,7 @@ __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
   constexpr int NR = walked_rows<LV, RH>();
   __shared__ Raw8<T> prev[NR * 64];
   __shared__ float pbuf[kPartialChunk * LV * 10];
+  __shared__ float red[8 * LV * 10];
   const int lane = threadIdx.x;
   const int li = lane & 15;
   const int seg = lane >> 4;
@@ -443,8 +449,8 @@ __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
     // past column W of the last walked row stays inside the frame
     const int64_t below = (int64_t)d.H - row0 - NR;
     const bool fast = d.vec && below >= 1 && below * d.row_stride >= 8;
-    if (fast) band_walk<T, LV, RH, false>(d, row0, c_lane, lane, part, local, prev, pbuf);
-    else band_walk<T, LV, RH, true>(d, row0, c_lane, lane, part, local, prev, pbuf);
+    if (fast) band_walk<T, LV, RH, false>(d, row0, c_lane, lane, part, local, prev, pbuf, red);
+    else band_walk<T, LV, RH, true>(d, row0, c_lane, lane, part, local, prev, pbuf, red);
   }
 }
 

@@ -299,18 +299,20 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // Built-in launch shape per (dtype, levels), from the tuning sweep of the fused
 // pass (paper_1612_08825_amd/autotune.py) on MI355X.
 // Sweep on MI355X (fused-pass ms; batched f16 workload at 4 levels, 64-stream
-// u8 mix at 3 levels): f16 best at 8 rows x 32 groups/CU (1.122 ms; 16 rows:
-// 1.298, 32 rows: 1.767), u8 best at 16 rows x 32 groups/CU (0.884 ms).
+// u8 mix at 3 levels): f16 best at 8 rows x 64 groups/CU (0.917 ms; 32 groups:
+// 0.994; 16 rows: 1.179, 32 rows: 1.661), u8 best at 16 rows x 32 groups/CU
+// (0.840 ms; 8 rows x 64: 0.868).  More groups than items means one item per
+// work-group, dispatched by the hardware.
 tc_ttc_tuning default_tuning(int dtype, int levels) {
   (void)levels;
   tc_ttc_tuning t;
   t.band_rows = dtype == TC_U8 ? 16 : 8;
-  t.groups_per_cu = 32;
+  t.groups_per_cu = dtype == TC_U8 ? 32 : 64;
   return t;
 }
 
 bool tuning_ok(const tc_ttc_tuning& t, int dtype, int levels) {
-  return t.groups_per_cu >= 1 && t.groups_per_cu <= 64 && fused_variant_exists(dtype, levels, t.band_rows);
+  return t.groups_per_cu >= 1 && t.groups_per_cu <= 256 && fused_variant_exists(dtype, levels, t.band_rows);
 }
 
 int validate_seq(const tc_seq& q, int dtype, int levels) {

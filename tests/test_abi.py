@@ -178,3 +178,20 @@ def test_ttc_plan_validation(lib):
     n = C.c_size_t()
     assert lib.tc_ttc_workspace_size(480, 640, 4, C.byref(n)) == 0 and n.value > 0
     assert lib.tc_ttc_workspace_size(480, 640, 5, C.byref(n)) == L.TC_EINVAL
+
+
+def test_ttc_tuning_defaults_and_rejections(lib):
+    t = L.TcTuning()
+    assert lib.tc_ttc_tuning_default(L.TC_F16, 4, C.byref(t)) == 0
+    assert (t.band_rows, t.groups_per_cu) == (8, 64)
+    assert lib.tc_ttc_tuning_default(L.TC_U8, 3, C.byref(t)) == 0
+    assert (t.band_rows, t.groups_per_cu) == (16, 32)
+    assert lib.tc_ttc_tuning_default(L.TC_F32, 3, C.byref(t)) == L.TC_EDTYPE
+    h = C.c_void_p()
+    arr = (L.TcSeq * 1)(_seq(64, 64, levels=3))
+    for rows, gpc in [(12, 32), (8, 0), (8, 257), (64, 32), (0, 8)]:
+        t.band_rows, t.groups_per_cu = rows, gpc
+        assert lib.tc_ttc_plan_create_ex(arr, 1, L.TC_U8, C.byref(t), C.byref(h)) == L.TC_EINVAL, (rows, gpc)
+        assert not h.value
+    # re-planning needs a plan and a valid batch
+    assert lib.tc_ttc_plan_reset(None, arr, 1) == L.TC_EINVAL

@@ -150,3 +150,51 @@ def test_batched_workload_sampled(api):
         g = s_i * 15 + t
         check_pair(recs[g * 4:(g + 1) * 4], picks[g], host[t], host[t + 1], 4, f"stream{s_i}")
     print(f"[ttc batched] worst sum err/sum|t| {WORST['sum']:.2e} rel C {WORST['C']:.2e} foe {WORST['foe']:.2e}")
+
+
+def _small_batch(dtype, case):
+    specs = synth.stream_specs(4, 3, 4, dtype, sizes=[(160, 120), (200, 96), (136, 80)], case=case)
+    return specs, [torch.from_numpy(np.ascontiguousarray(s.render())).cuda() for s in specs]
+
+
+@pytest.mark.parametrize("dtype,levels", [("u8", 3), ("f16", 4)])
+def test_every_tuning_candidate(api, dtype, levels):
+    """Work-groups per CU never change a result (bitwise); every band height
+    stays within the oracle tolerance."""
+    specs, vids = _small_batch(dtype, 9)
+    for rows in (8, 16, 32):
+        ref = None
+        for gpc in (1, 8, 64, 256):
+            recs, picks = api.ttc_solve_batched(vids, levels, tuning=(rows, gpc))
+            if ref is None:
+                ref = (recs.tobytes(), picks.tobytes())
+                q = 0
+                for s, v in zip(specs, vids):
+                    fr = _frames_np(v)
+                    for t in range(fr.shape[0] - 1):
+                        check_pair(recs[q * levels:(q + 1) * levels], picks[q], fr[t], fr[t + 1], levels,
+                                   f"rows{rows} {s.W}x{s.H} pair{t}")
+                        q += 1
+            else:
+                assert (recs.tobytes(), picks.tobytes()) == ref, (rows, gpc)
+
+
+def test_plan_reset_matches_fresh_plan(api):
+    _, a = _small_batch("u8", 21)
+    specsb, b = _small_batch("u8", 22)
+    b = b[:2]
+    plan = api.TTCPlan([api.seq_from_frames(v, 3) for v in a], torch.uint8, keep=a)
+    plan.run()
+    torch.cuda.synchronize()
+    ra = [x.tobytes() for x in plan.results()]
+    plan.reset([api.seq_from_frames(v, 3) for v in b], keep=b)
+    plan.run()
+    torch.cuda.synchronize()
+    rb = [x.tobytes() for x in plan.results()]
+    fresh = [x.tobytes() for x in api.ttc_solve_batched(b, 3)]
+    assert rb == fresh
+    plan.reset([api.seq_from_frames(v, 3) for v in a], keep=a)
+    plan.run()
+    torch.cuda.synchronize()
+    assert [x.tobytes() for x in plan.results()] == ra
+    plan.close()
