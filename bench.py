@@ -139,7 +139,9 @@ def cpu_baseline(specs, budget_s):
 # ----------------------------------------------------------------------------- conv sweep
 def conv_sweep(api, torch, steps):
     """Direct convolution, full mode, FP32; buffers rotated over >= 1 GiB so that
-    the 256 MiB last-level cache cannot serve them."""
+    the 256 MiB last-level cache cannot serve them.  Timed as a replayed graph of
+    the launches (per-launch kernel time); the eager per-call time, which
+    includes the host's call overhead, is reported beside it."""
     import numpy as np
 
     from paper_1612_08825_amd import synth
@@ -168,13 +170,31 @@ def conv_sweep(api, torch, steps):
             api.conv_nd(xbufs[i % nbuf], kk, "full", out=ybufs[i % nbuf])
         e1.record()
         torch.cuda.synchronize()
+        ms_eager = e0.elapsed_time(e1) / reps
+        # the same launches captured once in a HIP graph: the host's per-call
+        # cost drops out, what remains is the kernels back to back
+        ref = ybufs[0].clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(reps):
+                api.conv_nd(xbufs[i % nbuf], kk, "full", out=ybufs[i % nbuf])
+        ybufs[0].zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(ybufs[0], ref))
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
+        del g
         flops = 2.0 * math.prod(xs) * math.prod(ks)
         gbps = nbytes / (ms * 1e-3) / 1e9
         tf = flops / (ms * 1e-3) / 1e12
         bound = "hbm" if nbytes / (HBM_PEAK_GBPS * 1e9) >= flops / (ALU_PEAK_TFLOPS * 1e12) else "alu"
         name = f"{'x'.join(map(str, xs))}*{'x'.join(map(str, ks))}"
-        out[name] = {"ms": round(ms, 5), "Gelem_per_s": round(math.prod(xs) / (ms * 1e-3) / 1e9, 2),
+        out[name] = {"ms": round(ms, 5), "ms_eager_calls": round(ms_eager, 5), "graph_matches_eager": same,
+                     "Gelem_per_s": round(math.prod(xs) / (ms * 1e-3) / 1e9, 2),
                      "GB_per_s": round(gbps, 1), "TFLOP_per_s": round(tf, 2), "bound": bound,
                      "frac": round(gbps / HBM_PEAK_GBPS if bound == "hbm" else tf / ALU_PEAK_TFLOPS, 3)}
         del xbufs, ybufs

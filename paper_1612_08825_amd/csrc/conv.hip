@@ -2,14 +2,21 @@
 //
 // y[n] = sum_t k[t] * x[n + off - t]  (true convolution; `off` selects the
 // output mode: 0 for full, (K-1)/2 for same, min(N,K)-1 for valid), with x read
-// as zero outside its extent.  Two kernels:
+// as zero outside its extent.  Three kernels:
+//   * conv2d_rows (FP32, contiguous rows, square kernels of 2, 3, 5 or 7
+//     taps): one wave per band of output rows, each input row loaded once per
+//     wave straight into registers (one 16-byte load per lane, windows
+//     assembled across lanes with DPP); described where it is defined.
 //   * conv2d_tiled: a 256-thread work-group stages a (64 + KH - 1) x (64 + KW - 1)
 //     input tile in LDS (zero-filled at the borders) and every thread keeps a
 //     4 x 4 block of outputs in registers; taps are read with scalar loads.
 //     For rank 3 the grid's z dimension is the output plane, and the kernel
 //     loops over the kernel's planes, re-staging the matching input plane.
 //   * conv_generic: one thread per output element of any rank <= 8.
-// Taps are visited in kernel-row-major order for every output element.
+// The tiled and generic kernels visit taps in kernel-row-major order for every
+// output element; conv2d_rows visits tap rows from last to first.
+#include <type_traits>
+
 #include "device_common.hpp"
 #include "internal.hpp"
 
@@ -225,6 +232,404 @@ hipError_t launch_tiled(int xdt, const Tile2D& t, int kwmax, dim3 grid, hipStrea
   }
 }
 
+// ---------------------------------------------------------------- row-streaming f32 kernel
+// FP32 images whose rows are contiguous, for the common kernel sizes (KH and
+// KW compile-time).  One wave per item: a band of R (8, or 4 for small
+// outputs) output rows by 4 * LO
+// output columns of one output plane; lane i < LO holds output columns
+// 4i .. 4i+3 of the band in registers.  The wave walks the band's R + KH - 1
+// input rows top to bottom and multiplies each into every output row of the
+// band it reaches; taps are wave-uniform and come through the scalar cache.
+//
+// Loads are what bounds this kernel (each vector-memory instruction costs the
+// texture addresser about the same whatever its width), so an input row costs
+// one 16-byte load per lane: lane i loads 4 consecutive columns ("its chunk"),
+// and the KW + 3 columns a lane needs (its window) are its chunk and the chunks
+// of the next NC - 1 lanes, moved across the wave with DPP.  The last NC - 1
+// lanes only load: their windows would reach past the wave, so LO = 65 - NC.
+// The window of lane i starts S columns into its chunk (S = 0..3 is the same
+// for every lane and row of a launch and is a template parameter).
+//
+// In waves whose chunks may leave the image, a lane whose chunk lies wholly
+// outside loads nothing, and a lane whose chunk straddles the edge loads it one
+// column at a time with buffer loads through a resource limited to the row,
+// which read zero left and right of the image; bands whose rows may leave the
+// image skip those rows.
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
+template <typename T> using cptr = __attribute__((address_space(4))) const T*;
+
+template <int KW, int S> constexpr int row_chunks() { return (S + KW + 3 + 3) / 4; }
+template <int KW, int S> constexpr int row_lanes_out() { return 65 - row_chunks<KW, S>(); }
+
+struct RowArgs {
+  const float* x;
+  int64_t xs0, xsd;  // row and plane strides (elements)
+  int H, W, D;
+  const float* k;    // contiguous [KD][KH][KW]
+  int KD;
+  float* y;
+  int64_t ys0, ysd;
+  int OH, OW, OD;
+  int off0, off1, offd;
+  int n_bands, n_cw;
+  int64_t n_items;   // OD * n_bands * n_cw
+};
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// Buffer resource over `bytes` bytes from `base` (gfx9 raw-buffer word 3:
+// 32-bit data format, no swizzle).  A buffer load whose offset is outside the
+// range returns zero without touching memory (on this chip the scalar offset
+// counts toward the range too).  So with the row start as base, W * 4 bytes as
+// range and the column (times 4, as an unsigned 32-bit lane value) as the
+// vector offset, every load of a column left or right of the image reads zero.
+// (Multi-dword buffer loads are not used: they need aligned offsets.)
+constexpr int kBufWord3 = 0x00020000;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
+}
+
+// Value of lane i + 1 (DPP wave_shl:1, whole wave); lane 63 receives 0.
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+
+// acc[j][c] += sum over taps of one kernel plane, for the band's input rows
+// i0 .. i0 + R + KH - 2 (output row j of the band takes input rows
+// i0 + j .. i0 + j + KH - 1 with tap rows KH - 1 .. 0).  EDGE: some lane's
+// chunk may reach outside the image (such a lane loads its chunk one
+// range-checked column at a time); ROWCHECK: input rows may lie outside the
+// image (uniform across the wave; they are skipped).
+template <int KH, int KW, int R, int S, bool EDGE, bool ROWCHECK>
+__device__ __forceinline__ void band_accumulate(float (&acc)[R][4], const float* plane, uint32_t row_bytes,
+                                                int chunk0, uint32_t lane_col, int64_t xs0, int H, int i0,
+                                                cptr<float> taps) {
+  constexpr int NW = KW + 3;
+  constexpr int NC = row_chunks<KW, S>();
+  static_for<0, R + KH - 1>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    const int row = i0 + t;
+    if (!ROWCHECK || (row >= 0 && row < H)) {
+      const float* rp = plane + (int64_t)row * xs0;
+      // this lane's chunk, then those of the next NC - 1 lanes
+      float ch[4 * NC];
+      const int cc = chunk0 + (int)lane_col;  // first column of the chunk
+      const int W = (int)(row_bytes >> 2);
+      if (!EDGE || (cc >= 0 && cc + 4 <= W)) {
+        const f4u v = *(const __attribute__((address_space(1))) f4u*)(rp + cc);
+        ch[0] = v.x;
+        ch[1] = v.y;
+        ch[2] = v.z;
+        ch[3] = v.w;
+      } else if (cc >= W || cc + 4 <= 0) {
+        ch[0] = ch[1] = ch[2] = ch[3] = 0.f;  // wholly outside: no load
+      } else {
+        // a chunk reaching outside the image: one range-checked load per column
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(rp, row_bytes);
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+          ch[d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(cc + d) * 4u, 0, 0));
+      }
+#pragma unroll
+      for (int k = 1; k < NC; ++k)
+#pragma unroll
+        for (int d = 0; d < 4; ++d) ch[4 * k + d] = from_next_lane(ch[4 * (k - 1) + d]);
+      float w[NW];
+#pragma unroll
+      for (int e = 0; e < NW; ++e) w[e] = ch[S + e];
+      static_for<cmax(0, t - KH + 1), cmin(R - 1, t) + 1>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int a = j + KH - 1 - t;  // tap row
+#pragma unroll
+        for (int b = 0; b < KW; ++b) {
+          const float kv = taps[a * KW + b];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[j][c] = fmaf(kv, w[c + KW - 1 - b], acc[j][c]);
+        }
+      });
+    }
+  });
+}
+
+// At least WPE waves per SIMD (<= 512 / WPE VGPRs): left alone, the compiler
+// issues every row load of the unrolled band up front and holds them all.
+template <int KH, int KW, int R, int S, int WPE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void conv2d_rows(RowArgs a) {
+  constexpr int LO = row_lanes_out<KW, S>();
+  const int lane = threadIdx.x;
+  const int64_t G = gridDim.x, g = blockIdx.x;
+  // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin; give each
+  // XCD a contiguous run of items, so vertically adjacent bands (which share
+  // KH - 1 input rows) meet in the same L2.  Items run across a band's column
+  // strips first, so that concurrent waves read whole row segments.
+  const int64_t item = (G % 8 == 0) ? (g % 8) * (G / 8) + g / 8 : g;
+  if (item >= a.n_items) return;
+  const int64_t per_plane = (int64_t)a.n_bands * a.n_cw;
+  const int od = (int)(item / per_plane);
+  const int rem = (int)(item - (int64_t)od * per_plane);
+  const int band = rem / a.n_cw;
+  const int cw = rem - band * a.n_cw;
+  const int o0 = band * R;
+  const int p_wave = cw * 4 * LO;
+  const int p_lane = p_wave + 4 * lane;
+  // first column of lane 0's chunk: lane i's window starts S columns into its
+  // chunk, at full column p_lane + off1 - (KW - 1)
+  const int chunk0 = p_wave + a.off1 - (KW - 1) - S;
+  const uint32_t lane_col = 4u * (uint32_t)lane;
+  const int i0 = o0 + a.off0 - (KH - 1);  // first input row of the band
+  const bool rows_in = i0 >= 0 && i0 + R + KH - 2 < a.H;
+  const bool cols_in = chunk0 >= 0 && chunk0 + 256 <= a.W;
+
+  float acc[R][4];
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[j][c] = 0.f;
+
+  const int nd = od + a.offd;  // full-result plane
+  for (int kd = 0; kd < a.KD; ++kd) {
+    const int xd = nd - kd;
+    if (xd < 0 || xd >= a.D) continue;  // uniform
+    const float* plane = a.x + (int64_t)xd * a.xsd;
+    const uint32_t row_bytes = (uint32_t)a.W * 4u;
+    const cptr<float> taps = (cptr<float>)(a.k) + kd * KH * KW;
+    if (rows_in && cols_in)
+      band_accumulate<KH, KW, R, S, false, false>(acc, plane, row_bytes, chunk0, lane_col, a.xs0, a.H, i0, taps);
+    else if (cols_in)
+      band_accumulate<KH, KW, R, S, false, true>(acc, plane, row_bytes, chunk0, lane_col, a.xs0, a.H, i0, taps);
+    else
+      band_accumulate<KH, KW, R, S, true, true>(acc, plane, row_bytes, chunk0, lane_col, a.xs0, a.H, i0, taps);
+  }
+
+  if (lane >= LO) return;
+  const gptr<float> yp = as_global(a.y) + (int64_t)od * a.ysd;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    const int o = o0 + j;
+    if (o >= a.OH) break;
+    const gptr<float> yr = yp + (int64_t)o * a.ys0 + p_lane;
+    if (p_lane + 3 < a.OW) {
+      f4u v;
+      v.x = acc[j][0];
+      v.y = acc[j][1];
+      v.z = acc[j][2];
+      v.w = acc[j][3];
+      *(__attribute__((address_space(1))) f4u*)yr = v;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (p_lane + c < a.OW) yr[c] = acc[j][c];
+    }
+  }
+}
+
+// Large square kernels (15 x 15): the unrolled band of conv2d_rows would need
+// all KH * KW taps live in scalar registers at once.  Here the band's input
+// rows are a runtime loop with a rolling window of KH accumulator rows: at
+// input row t, accumulator u holds band output row t - (KH - 1) + u, which
+// takes tap row u; after the row, accumulator 0 is complete, is stored, and
+// the window moves down one row.  Each input row is loaded once per wave (the
+// same chunk + DPP scheme as conv2d_rows, one row ahead) and multiplied into
+// all KH rows of the window; the taps are re-read from the scalar cache every
+// row (an empty asm keeps the compiler from holding all of them).  Window rows
+// outside the band or the output are not updated, so a band of RB rows costs
+// RB * KH * KW multiply-adds per lane column, as the convolution itself.
+template <int KH, int KW, int RB, int S>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void conv2d_rows_roll(RowArgs a) {
+  constexpr int NC = row_chunks<KW, S>();
+  constexpr int LO = row_lanes_out<KW, S>();
+  constexpr int NW = KW + 3;
+  const int lane = threadIdx.x;
+  const int64_t G = gridDim.x, g = blockIdx.x;
+  const int64_t item = (G % 8 == 0) ? (g % 8) * (G / 8) + g / 8 : g;
+  if (item >= a.n_items) return;
+  const int64_t per_plane = (int64_t)a.n_bands * a.n_cw;
+  const int od = (int)(item / per_plane);
+  const int rem = (int)(item - (int64_t)od * per_plane);
+  const int band = rem / a.n_cw;
+  const int cw = rem - band * a.n_cw;
+  const int o0 = band * RB;
+  const int p_wave = cw * 4 * LO;
+  const int p_lane = p_wave + 4 * lane;
+  const int chunk0 = p_wave + a.off1 - (KW - 1) - S;
+  const int cc = chunk0 + 4 * lane;  // first column of this lane's chunk
+  const bool chunk_in = cc >= 0 && cc + 4 <= a.W;
+  const uint32_t row_bytes = (uint32_t)a.W * 4u;
+  const int i0 = o0 + a.off0 - (KH - 1);
+  const int n_out = RB < a.OH - o0 ? RB : a.OH - o0;  // band rows inside the output
+  const int n_rows = n_out + KH - 1;
+  const gptr<float> yp = as_global(a.y) + (int64_t)od * a.ysd;
+  const bool store_lane = lane < LO;
+
+  // only one kernel plane per output plane is supported here (2-D)
+  const float* plane = a.x;
+  cptr<float> taps = (cptr<float>)(a.k);
+
+  auto load_chunk = [&](int row, float (&c4)[4]) {
+    if (row < 0 || row >= a.H) {  // uniform
+      c4[0] = c4[1] = c4[2] = c4[3] = 0.f;
+      return;
+    }
+    const float* rp = plane + (int64_t)row * a.xs0;
+    if (chunk_in) {
+      const f4u v = *(const __attribute__((address_space(1))) f4u*)(rp + cc);
+      c4[0] = v.x;
+      c4[1] = v.y;
+      c4[2] = v.z;
+      c4[3] = v.w;
+    } else if (cc >= a.W || cc + 4 <= 0) {
+      c4[0] = c4[1] = c4[2] = c4[3] = 0.f;  // wholly outside: no load
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(rp, row_bytes);
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        c4[d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(cc + d) * 4u, 0, 0));
+    }
+  };
+
+  float acc[KH][4];
+#pragma unroll
+  for (int u = 0; u < KH; ++u)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[u][c] = 0.f;
+
+  float nxt[4];
+  load_chunk(i0, nxt);
+  for (int t = 0; t < n_rows; ++t) {
+    float ch[4 * NC];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ch[d] = nxt[d];
+    if (t + 1 < n_rows) load_chunk(i0 + t + 1, nxt);
+#pragma unroll
+    for (int k = 1; k < NC; ++k)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) ch[4 * k + d] = from_next_lane(ch[4 * (k - 1) + d]);
+    float w[NW];
+#pragma unroll
+    for (int e = 0; e < NW; ++e) w[e] = ch[S + e];
+    asm volatile("" : "+s"(taps));
+    // accumulator u is band output row t - (KH - 1) + u: only rows inside the
+    // band and the image are worth updating (uniform bounds)
+    const int u_lo = (KH - 1 - t) > 0 ? KH - 1 - t : 0;
+    const int j_top = (RB < a.OH - o0 ? RB : a.OH - o0) - 1;  // last band row to produce
+    const int u_hi = j_top + (KH - 1) - t;
+#pragma unroll
+    for (int u = 0; u < KH; ++u) {
+      if (u < u_lo || u > u_hi) continue;
+#pragma unroll
+      for (int b = 0; b < KW; ++b) {
+        const float kv = taps[u * KW + b];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[u][c] = fmaf(kv, w[c + KW - 1 - b], acc[u][c]);
+      }
+    }
+    // accumulator 0 is band output row t - (KH - 1)
+    const int j = t - (KH - 1);
+    const int o = o0 + j;
+    if (j >= 0 && o < a.OH && store_lane) {
+      const gptr<float> yr = yp + (int64_t)o * a.ys0 + p_lane;
+      if (p_lane + 3 < a.OW) {
+        f4u v;
+        v.x = acc[0][0];
+        v.y = acc[0][1];
+        v.z = acc[0][2];
+        v.w = acc[0][3];
+        *(__attribute__((address_space(1))) f4u*)yr = v;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (p_lane + c < a.OW) yr[c] = acc[0][c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u + 1 < KH; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[u][c] = acc[u + 1][c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[KH - 1][c] = 0.f;
+  }
+}
+
+template <int KH, int KW, int RB, int S>
+hipError_t launch_roll_s(RowArgs ra, hipStream_t s) {
+  constexpr int LO = row_lanes_out<KW, S>();
+  ra.n_bands = (ra.OH + RB - 1) / RB;
+  ra.n_cw = (ra.OW + 4 * LO - 1) / (4 * LO);
+  ra.n_items = (int64_t)ra.OD * ra.n_bands * ra.n_cw;
+  const int64_t grid = (ra.n_items + 7) / 8 * 8;
+  hipLaunchKernelGGL((conv2d_rows_roll<KH, KW, RB, S>), dim3((unsigned)grid), dim3(64), 0, s, ra);
+  return hipGetLastError();
+}
+
+template <int KH, int KW, int RB>
+hipError_t launch_roll_t(const RowArgs& ra, hipStream_t s) {
+  switch ((((ra.off1 - (KW - 1)) % 4) + 4) % 4) {
+    case 0: return launch_roll_s<KH, KW, RB, 0>(ra, s);
+    case 1: return launch_roll_s<KH, KW, RB, 1>(ra, s);
+    case 2: return launch_roll_s<KH, KW, RB, 2>(ra, s);
+    default: return launch_roll_s<KH, KW, RB, 3>(ra, s);
+  }
+}
+
+template <int KH, int KW, int R, int S>
+hipError_t launch_rows_s(RowArgs ra, hipStream_t s) {
+  constexpr int LO = row_lanes_out<KW, S>();
+  ra.n_bands = (ra.OH + R - 1) / R;
+  ra.n_cw = (ra.OW + 4 * LO - 1) / (4 * LO);
+  ra.n_items = (int64_t)ra.OD * ra.n_bands * ra.n_cw;
+  const int64_t grid = (ra.n_items + 7) / 8 * 8;
+  hipLaunchKernelGGL((conv2d_rows<KH, KW, R, S, 4>), dim3((unsigned)grid), dim3(64), 0, s, ra);
+  return hipGetLastError();
+}
+
+template <int KH, int KW, int R>
+hipError_t launch_rows_t(const RowArgs& ra, hipStream_t s) {
+  // the window's offset inside a chunk: (off1 - (KW - 1)) mod 4
+  switch ((((ra.off1 - (KW - 1)) % 4) + 4) % 4) {
+    case 0: return launch_rows_s<KH, KW, R, 0>(ra, s);
+    case 1: return launch_rows_s<KH, KW, R, 1>(ra, s);
+    case 2: return launch_rows_s<KH, KW, R, 2>(ra, s);
+    default: return launch_rows_s<KH, KW, R, 3>(ra, s);
+  }
+}
+
+// The (KH, KW) pairs the row-streaming kernels are built for (15 x 15 only
+// for 2-D: the rolling kernel takes one kernel plane).
+bool rows_variant(int KH, int KW, int rank) {
+  return KH == KW && (KH == 2 || KH == 3 || KH == 5 || KH == 7 || (KH == 15 && rank == 2));
+}
+
+// Items (waves) a band height gives; the band height is the tallest that still
+// gives about two waves per SIMD (2048 on 256 CUs), else the shortest.
+int64_t row_items(const RowArgs& ra, int rb, int lanes_out) {
+  return (int64_t)ra.OD * ((ra.OH + rb - 1) / rb) * ((ra.OW + 4 * lanes_out - 1) / (4 * lanes_out));
+}
+constexpr int64_t kTargetItems = 2048;
+
+hipError_t launch_rows(const RowArgs& ra, int KH, hipStream_t s) {
+  if (KH == 15) {
+    if (row_items(ra, 32, 59) >= kTargetItems) return launch_roll_t<15, 15, 32>(ra, s);
+    if (row_items(ra, 16, 59) >= kTargetItems) return launch_roll_t<15, 15, 16>(ra, s);
+    return launch_roll_t<15, 15, 8>(ra, s);
+  }
+  const bool small = row_items(ra, 8, 61) < kTargetItems;
+  switch (KH) {
+    case 2: return small ? launch_rows_t<2, 2, 4>(ra, s) : launch_rows_t<2, 2, 8>(ra, s);
+    case 3: return small ? launch_rows_t<3, 3, 4>(ra, s) : launch_rows_t<3, 3, 8>(ra, s);
+    case 5: return small ? launch_rows_t<5, 5, 4>(ra, s) : launch_rows_t<5, 5, 8>(ra, s);
+    case 7: return small ? launch_rows_t<7, 7, 4>(ra, s) : launch_rows_t<7, 7, 8>(ra, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
@@ -235,9 +640,47 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
   }
   if (n_out == 0) return hipSuccess;
 
-  // 2-D and 3-D: the LDS-tiled kernels, for kernel rows up to 16 taps and
-  // kernel heights that keep the staged tile within 64 KiB of LDS.
   const int r = c.ndim;
+  // 2-D and 3-D FP32 with contiguous rows and a common kernel size: the
+  // row-streaming kernel.
+  if ((r == 2 || r == 3) && c.xdt == TC_F32 && c.xstride[r - 1] == 1 && c.ystride[r - 1] == 1 &&
+      rows_variant((int)c.kshape[r - 2], (int)c.kshape[r - 1], r) && c.xshape[r - 1] < (1LL << 28) &&
+      c.xshape[r - 2] < (1LL << 30) && c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&
+      c.off[r - 1] < (1LL << 30) && c.off[r - 2] < (1LL << 30) &&
+      (r == 2 || (c.xshape[0] < (1LL << 30) && c.yshape[0] < (1LL << 20) && c.kshape[0] < (1LL << 20) &&
+                  c.off[0] < (1LL << 30)))) {
+    RowArgs ra{};
+    ra.x = static_cast<const float*>(c.x);
+    ra.xs0 = c.xstride[r - 2];
+    ra.H = (int)c.xshape[r - 2];
+    ra.W = (int)c.xshape[r - 1];
+    ra.k = static_cast<const float*>(c.k);
+    ra.y = static_cast<float*>(c.y);
+    ra.ys0 = c.ystride[r - 2];
+    ra.OH = (int)c.yshape[r - 2];
+    ra.OW = (int)c.yshape[r - 1];
+    ra.off0 = (int)c.off[r - 2];
+    ra.off1 = (int)c.off[r - 1];
+    if (r == 3) {
+      ra.xsd = c.xstride[0];
+      ra.ysd = c.ystride[0];
+      ra.D = (int)c.xshape[0];
+      ra.KD = (int)c.kshape[0];
+      ra.OD = (int)c.yshape[0];
+      ra.offd = (int)c.off[0];
+    } else {
+      ra.xsd = 0;
+      ra.ysd = 0;
+      ra.D = 1;
+      ra.KD = 1;
+      ra.OD = 1;
+      ra.offd = 0;
+    }
+    return launch_rows(ra, (int)c.kshape[r - 2], s);
+  }
+
+  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 16
+  // taps and kernel heights that keep the staged tile within 64 KiB of LDS.
   const bool tiled_ok = (r == 2 || r == 3) && small_taps && c.kshape[r - 1] <= 16 && c.kshape[r - 2] <= 64 &&
                         c.xshape[r - 1] < (1LL << 30) && c.xshape[r - 2] < (1LL << 30) &&
                         c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&

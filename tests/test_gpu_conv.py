@@ -38,7 +38,10 @@ def _check_float(y, x, k, mode, tag):
 
 
 SHAPES_2D = [((70, 130), (3, 3)), ((129, 65), (7, 7)), ((100, 77), (15, 15)), ((5, 6), (9, 11)),
-             ((64, 64), (1, 1)), ((1, 200), (1, 5)), ((67, 67), (2, 5)), ((40, 33), (16, 16)), ((33, 19), (20, 3))]
+             ((64, 64), (1, 1)), ((1, 200), (1, 5)), ((67, 67), (2, 5)), ((40, 33), (16, 16)), ((33, 19), (20, 3)),
+             # several bands and 256-column waves with ragged tails (interior items take the unchecked path)
+             ((61, 777), (3, 3)), ((45, 600), (2, 2)), ((37, 530), (5, 5)), ((29, 1100), (7, 7)), ((3, 5), (5, 5)),
+             ((70, 560), (15, 15)), ((9, 300), (15, 15))]
 
 
 @pytest.mark.parametrize("xs,ks", SHAPES_2D)
@@ -88,7 +91,8 @@ def test_conv_strided_views(api):
     assert float(big[0, 0]) == -7.0 and float(big[199, 199]) == -7.0  # nothing written outside the view
 
 
-@pytest.mark.parametrize("xs,ks", [((9, 70, 66), (3, 3, 3)), ((3, 5, 4), (4, 6, 5)), ((6, 31, 29), (2, 7, 1))])
+@pytest.mark.parametrize("xs,ks", [((9, 70, 66), (3, 3, 3)), ((3, 5, 4), (4, 6, 5)), ((6, 31, 29), (2, 7, 1)),
+                                   ((5, 21, 600), (3, 3, 3)), ((4, 19, 300), (2, 5, 5))])
 @pytest.mark.parametrize("mode", ["full", "same", "valid"])
 def test_conv3d(api, xs, ks, mode):
     try:
