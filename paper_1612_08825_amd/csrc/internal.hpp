@@ -71,6 +71,8 @@ struct FusedLaunch {
   int levels;       // 1..4
   int band_rows;    // 8, 16 or 32
   const SeqDesc* table;  // device table, or nullptr to use `inl`
+  const int32_t* item_seq;  // stream of every work item (with `table`)
+  const int32_t* pair_seq;  // stream of every pair (with `table`)
   int n_seqs;
   SeqDesc inl;
   int64_t n_items;

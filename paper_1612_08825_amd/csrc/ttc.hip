@@ -46,6 +46,8 @@ namespace {
 
 struct FusedArgs {
   const SeqDesc* table;
+  const int32_t* item_seq;
+  const int32_t* pair_seq;
   int n_seqs;
   SeqDesc inl;
   int64_t n_items;
@@ -94,26 +96,17 @@ __device__ __forceinline__ SeqDesc load_desc(gptr<const SeqDesc> p) {
   return d;
 }
 
+// The stream of a work item or pair: one load from the plan's index arrays.
 __device__ __forceinline__ SeqDesc seq_for_item(const FusedArgs& a, int64_t item) {
   if (a.table == nullptr) return a.inl;
-  const gptr<const SeqDesc> tab = as_global(a.table);
-  int lo = 0, hi = a.n_seqs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab[mid].item_begin <= item) lo = mid; else hi = mid - 1;
-  }
-  return load_desc(tab + lo);
+  const int32_t i = uni(as_global(a.item_seq)[item]);
+  return load_desc(as_global(a.table) + i);
 }
 
 __device__ __forceinline__ SeqDesc seq_for_pair(const FusedArgs& a, int64_t pair) {
   if (a.table == nullptr) return a.inl;
-  const gptr<const SeqDesc> tab = as_global(a.table);
-  int lo = 0, hi = a.n_seqs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab[mid].pair_begin <= pair) lo = mid; else hi = mid - 1;
-  }
-  return load_desc(tab + lo);
+  const int32_t i = uni(as_global(a.pair_seq)[pair]);
+  return load_desc(as_global(a.table) + i);
 }
 
 // Accumulate the cubes of one row of one level.  hd*, hs*, hD* are the horizontal
@@ -544,17 +537,20 @@ __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __r
   const SeqDesc d = seq_for_pair(a, gp);
   const int64_t p = gp - d.pair_begin;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ float red_hi[4][10], red_lo[4][10];
   __shared__ double sums[LV][10];
   __shared__ tc_ttc_level res[LV];
 
-  for (int l = 0; l < LV; ++l) {
+  // wave l reduces level l: each lane adds every 64th wave item's partials with
+  // TwoSum compensation, then the lanes' (hi, lo) pairs are merged in a fixed
+  // butterfly order
+  if (wave < LV) {
+    const int l = wave;
     float hi[10], lo[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) hi[q] = lo[q] = 0.f;
     const gptr<const float> base =
         as_global(a.partials + d.partial_begin + (p * LV + l) * (int64_t)d.n_witems * 10);
-    for (int w = tid; w < d.n_witems; w += 256) {
+    for (int w = lane; w < d.n_witems; w += 64) {
 #pragma unroll
       for (int q = 0; q < 10; ++q) comp_add(hi[q], lo[q], base[(int64_t)w * 10 + q]);
     }
@@ -567,19 +563,12 @@ __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __r
         comp_merge(hi[q], lo[q], h2, l2);
       }
     }
-    if (lane == 0)
-      for (int q = 0; q < 10; ++q) {
-        red_hi[wave][q] = hi[q];
-        red_lo[wave][q] = lo[q];
-      }
-    __syncthreads();
-    if (tid < 10) {
-      float h = red_hi[0][tid], lo0 = red_lo[0][tid];
-      for (int wv = 1; wv < 4; ++wv) comp_merge(h, lo0, red_hi[wv][tid], red_lo[wv][tid]);
-      sums[l][tid] = ldexp((double)h + (double)lo0, -sum_scale_exp(l, tid));
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 10; ++q) sums[l][q] = ldexp((double)hi[q] + (double)lo[q], -sum_scale_exp(l, q));
     }
-    __syncthreads();
   }
+  __syncthreads();
 
   if (tid < LV) {
     tc_ttc_level r;
@@ -610,6 +599,8 @@ __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __r
 FusedArgs make_args(const FusedLaunch& f) {
   FusedArgs a;
   a.table = f.table;
+  a.item_seq = f.item_seq;
+  a.pair_seq = f.pair_seq;
   a.n_seqs = f.n_seqs;
   a.inl = f.inl;
   a.n_items = f.n_items;

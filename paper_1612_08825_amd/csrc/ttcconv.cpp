@@ -280,7 +280,7 @@ struct tc_ttc_plan {
   int levels = 0;
   int band_rows = 0;
   int groups_per_cu = 0;
-  int capacity = 0;  // table entries the pinned buffer holds
+  size_t capacity = 0;  // bytes the pinned table buffer holds
   int n_seqs = 0;
   int64_t n_items = 0;
   int64_t n_pairs = 0;
@@ -288,7 +288,9 @@ struct tc_ttc_plan {
   size_t table_bytes = 0;
   size_t ws_bytes = 0;
   int grid = 0;
-  SeqDesc* table = nullptr;  // pinned host copy
+  size_t item_index_off = 0;  // byte offsets of the item -> stream and pair -> stream
+  size_t pair_index_off = 0;  // index arrays inside the table region
+  SeqDesc* table = nullptr;   // pinned host copy of the table region
 };
 
 namespace {
@@ -362,25 +364,16 @@ int persistent_grid(int64_t n_items, int groups_per_cu) {
 
 }  // namespace
 
-// (Re)builds the plan's work table for `seqs` in its pinned buffer.
+// (Re)builds the plan's table region for `seqs` in its pinned buffer:
+// [SeqDesc per stream | int32 stream of every work item | int32 stream of
+// every pair], each part 256-byte aligned, so that a work item or a pair finds
+// its stream with one load.
 static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
-  if (n_seqs > p->capacity) {
-    if (p->table) (void)hipHostFree(p->table);
-    p->table = nullptr;
-    p->capacity = 0;
-    const size_t bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
-    if (hipHostMalloc(reinterpret_cast<void**>(&p->table), bytes, hipHostMallocDefault) != hipSuccess) {
-      p->table = nullptr;
-      return TC_EDEVICE;
-    }
-    p->capacity = n_seqs;
-  }
-  p->n_seqs = n_seqs;
-  p->table_bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
-  memset(p->table, 0, sizeof(SeqDesc) * (size_t)n_seqs);
+  std::vector<SeqDesc> descs((size_t)n_seqs);
   int64_t items = 0, pairs = 0, floats = 0;
   for (int i = 0; i < n_seqs; ++i) {
-    SeqDesc& d = p->table[i];
+    SeqDesc& d = descs[(size_t)i];
+    memset(&d, 0, sizeof d);
     fill_desc(d, seqs[i], p->dtype, p->band_rows);
     d.item_begin = items;
     d.pair_begin = pairs;
@@ -389,6 +382,34 @@ static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
     pairs += d.n_frames - 1;
     floats += (int64_t)(d.n_frames - 1) * p->levels * d.n_witems * 10;
   }
+  if (items > INT32_MAX || pairs > INT32_MAX) return TC_EINVAL;
+  const size_t desc_bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
+  const size_t item_bytes = align_up(sizeof(int32_t) * (size_t)items);
+  const size_t pair_bytes = align_up(sizeof(int32_t) * (size_t)pairs);
+  const size_t bytes = desc_bytes + item_bytes + pair_bytes;
+  if (bytes > p->capacity) {
+    if (p->table) (void)hipHostFree(p->table);
+    p->table = nullptr;
+    p->capacity = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&p->table), bytes, hipHostMallocDefault) != hipSuccess) {
+      p->table = nullptr;
+      return TC_EDEVICE;
+    }
+    p->capacity = bytes;
+  }
+  char* base = reinterpret_cast<char*>(p->table);
+  memcpy(base, descs.data(), sizeof(SeqDesc) * (size_t)n_seqs);
+  int32_t* item_seq = reinterpret_cast<int32_t*>(base + desc_bytes);
+  int32_t* pair_seq = reinterpret_cast<int32_t*>(base + desc_bytes + item_bytes);
+  for (int i = 0; i < n_seqs; ++i) {
+    const SeqDesc& d = descs[(size_t)i];
+    for (int64_t k = 0; k < d.n_witems; ++k) item_seq[d.item_begin + k] = i;
+    for (int64_t k = 0; k < d.n_frames - 1; ++k) pair_seq[d.pair_begin + k] = i;
+  }
+  p->n_seqs = n_seqs;
+  p->item_index_off = desc_bytes;
+  p->pair_index_off = desc_bytes + item_bytes;
+  p->table_bytes = bytes;
   p->n_items = items;
   p->n_pairs = pairs;
   p->n_partial_floats = floats;
@@ -460,7 +481,7 @@ extern "C" int tc_ttc_plan_info(const tc_ttc_plan* plan, size_t* ws_bytes, int64
 extern "C" int tc_ttc_plan_upload(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, void* stream) {
   if (!plan || !ws) return TC_EINVAL;
   if (ws_bytes < plan->ws_bytes) return TC_ENOMEM;
-  return hip_status(hipMemcpyAsync(ws, plan->table, sizeof(SeqDesc) * (size_t)plan->n_seqs, hipMemcpyHostToDevice,
+  return hip_status(hipMemcpyAsync(ws, plan->table, plan->table_bytes, hipMemcpyHostToDevice,
                                    reinterpret_cast<hipStream_t>(stream)));
 }
 
@@ -474,6 +495,8 @@ extern "C" int tc_ttc_plan_run_phase(const tc_ttc_plan* plan, void* ws, size_t w
   f.levels = plan->levels;
   f.band_rows = plan->band_rows;
   f.table = reinterpret_cast<const SeqDesc*>(ws);
+  f.item_seq = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ws) + plan->item_index_off);
+  f.pair_seq = reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(ws) + plan->pair_index_off);
   f.n_seqs = plan->n_seqs;
   f.n_items = plan->n_items;
   f.n_pairs = plan->n_pairs;
