@@ -11,12 +11,13 @@
 //     four 16-lane segments; lane i of a segment holds 8 adjacent base columns
 //     (one level-3 column).  Lane 15 of each segment only provides its left
 //     column to lane 14 (the segment owns 120 columns).
-//   * The wave walks the stream's frames in time.  The previous frame's band
-//     stays in LDS in its packed u8 / f16 form (each lane reads and writes only
-//     its own slots), so every frame is read from memory once; each new frame
-//     row is combined with the stored one as the temporal sum S = P0 + P1 and
-//     difference D = P1 - P0 (for f16 frames one mixed-precision FMA each).  The current frame's rows are prefetched a few
-//     rows ahead into registers.
+//   * The wave walks the stream's frames in time.  Each row of a new frame is
+//     combined with the same row of the previous frame as the temporal sum
+//     S = P0 + P1 and difference D = P1 - P0 (for f16 frames one
+//     mixed-precision FMA each).  New rows are prefetched a few rows ahead into
+//     registers; the previous frame's band stays in LDS (u8) or is read again,
+//     from the caches, through a second prefetch ring (f16), so HBM sees every
+//     frame once.
 //   * Rows are walked top to bottom.  Horizontal neighbour sums/differences of
 //     S and D give the derivative cube by one more vertical step.  Because the
 //     pyramid is linear, the 2x2 sums of S and D at even columns *are* the next
@@ -166,10 +167,17 @@ __device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&
   }
 }
 
-// The rows of a band are walked in groups of G rows (8 with four levels, so that
-// every level's row pattern repeats inside a group; 4 otherwise).  Rows walked:
-// the band plus the halo of 2^(LV-1) rows below it, rounded up to whole groups.
-template <int LV> constexpr int row_group() { return LV >= 4 ? 8 : 4; }
+// Where the previous frame's band rows come from: u8 rows (8 bytes per lane)
+// are kept in LDS, each lane reading and writing only its own slots; f16 rows
+// (16 bytes per lane) would hold enough LDS to cap the waves per CU, so they are
+// read again from the caches through a second prefetch ring (the tuning sweep
+// measured each choice faster for its element type).
+template <typename T> constexpr bool kPrevInLds = sizeof(T) == 1;
+
+// The rows of a band are walked in groups of G = 4 rows (the depth of the
+// prefetch rings).  Rows walked: the band plus the halo of 2^(LV-1) rows below
+// it, rounded up to whole groups.
+template <int LV> constexpr int row_group() { return 4; }
 template <int LV, int RH> constexpr int walked_rows() {
   return ((RH + (1 << (LV - 1))) + row_group<LV>() - 1) / row_group<LV>() * row_group<LV>();
 }
@@ -190,12 +198,14 @@ __device__ __forceinline__ void static_for(F&& f) {
 // One wave walks one band of one stream through all frames.  CHECK: the band
 // touches the bottom of the frame (rows may be missing) or the stream is not
 // vector-aligned; otherwise every walked row exists and the 8-pixel vector load
-// of a lane may run past column W into rows that exist.  `prev` is this wave's
-// LDS band store, [NR][64] packed rows.
+// of a lane may run past column W into rows that exist.
 //
-// Rows are prefetched G rows ahead through a ring of G registers that crosses
-// frame boundaries: while the last rows of frame k are processed, the first
-// rows of frame k+1 are already in flight.
+// Rows of the current frame are prefetched G rows ahead through a register
+// ring that crosses frame boundaries: while the last rows of frame k are
+// processed, the first rows of frame k+1 are already in flight.  The previous
+// frame's rows are either the band store `prev` in LDS ([NR][64] packed rows)
+// or a second ring of the same kind; in the latter case they were read by this
+// wave one frame earlier and come back from the caches, not from HBM.
 template <typename T, int LV, int RH, bool CHECK>
 __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane, int lane, float* part,
                                           int64_t witem, Raw8<T>* prev, float* pbuf, float* red) {
@@ -247,13 +257,19 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
     }
   };
 
-  // frame 0 into the band store, the first group of frame 1 into the ring
-  for (int w = 0; w < NR; ++w) {
-    Raw8<T> r;
-    load_row(r, band0, w);
-    prev[w * 64 + lane] = r;
+  // the first group of frame 1 into the ring; the previous frame: frame 0
+  // into the band store (LDS) or its first group into the second ring
+  Raw8<T> ahead[G], ahead_prev[G];
+  if constexpr (kPrevInLds<T>) {
+    for (int w = 0; w < NR; ++w) {
+      Raw8<T> r;
+      load_row(r, band0, w);
+      prev[w * 64 + lane] = r;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < G; ++i) load_row(ahead_prev[i], band0, i);
   }
-  Raw8<T> ahead[G];
 #pragma unroll
   for (int i = 0; i < G; ++i) load_row(ahead[i], band0 + fs_b, i);
 
@@ -281,18 +297,30 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
         constexpr int w = decltype(wc)::value;
         constexpr int i = w % G;
         const Raw8<T> cur = ahead[i];
-        if constexpr (w + G < NR) load_row(ahead[i], fk, w + G);
-        else load_row(ahead[i], fnext, w + G - NR);
-        if (!CHECK || row0 + w < H) {
-          const Raw8<T> old = prev[w * 64 + lane];
+        Raw8<T> old;
+        if constexpr (kPrevInLds<T>) {
+          if constexpr (w + G < NR) load_row(ahead[i], fk, w + G);
+          else load_row(ahead[i], fnext, w + G - NR);
+          old = prev[w * 64 + lane];
           prev[w * 64 + lane] = cur;
+        } else {
+          old = ahead_prev[i];
+          if constexpr (w + G < NR) {
+            load_row(ahead[i], fk, w + G);
+            load_row(ahead_prev[i], fk - fs_b, w + G);
+          } else {
+            load_row(ahead[i], fnext, w + G - NR);
+            load_row(ahead_prev[i], fnext - fs_b, w + G - NR);
+          }
+        }
+        if (!CHECK || row0 + w < H) {
           float S[8], D[8];
           cur.sum_diff(old, S, D);
           float hs0[8], hd0[8], hD0[8];
           horizontals<8>(S, D, hs0, hd0, hD0);
           if constexpr (w >= 1 && w <= RH)
             cubes_dispatch<8>(edge[0], acc[0], hd0p, hd0, hs0p, hs0, hD0p, hD0, ncv[0], xb[0], yb[0] + (float)w);
-          if constexpr (LV >= 2 && (i & 1) == 1) {
+          if constexpr (LV >= 2 && (w & 1) == 1) {
             float U1[4], V1[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -304,7 +332,7 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
             constexpr int lr1 = w >> 1;  // level-1 row just formed, counted from the band top
             if constexpr (lr1 >= 1 && lr1 <= (RH >> 1))
               cubes_dispatch<4>(edge[1], acc[1], hd1p, hd1, hs1p, hs1, hD1p, hD1, ncv[1], xb[1], yb[1] + (float)lr1);
-            if constexpr (LV >= 3 && (i & 3) == 3) {
+            if constexpr (LV >= 3 && (w & 3) == 3) {
               float U2[2], V2[2];
 #pragma unroll
               for (int c = 0; c < 2; ++c) {
@@ -316,7 +344,7 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
               constexpr int lr2 = w >> 2;
               if constexpr (lr2 >= 1 && lr2 <= (RH >> 2))
                 cubes_dispatch<2>(edge[2], acc[2], hd2p, hd2, hs2p, hs2, hD2p, hD2, ncv[2], xb[2], yb[2] + (float)lr2);
-              if constexpr (LV >= 4 && (i & 7) == 7) {
+              if constexpr (LV >= 4 && (w & 7) == 7) {
                 float U3[1], V3[1];
                 U3[0] = hs2p[0] + hs2[0];
                 V3[0] = hD2p[0] + hD2[0];
@@ -415,7 +443,7 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
 template <typename T, int LV, int RH>
 __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
   constexpr int NR = walked_rows<LV, RH>();
-  __shared__ Raw8<T> prev[NR * 64];
+  __shared__ Raw8<T> prev[kPrevInLds<T> ? NR * 64 : 1];
   __shared__ float pbuf[kPartialChunk * LV * 10];
   __shared__ float red[8 * LV * 10];
   const int lane = threadIdx.x;
