@@ -15,9 +15,8 @@
 //     combined with the same row of the previous frame as the temporal sum
 //     S = P0 + P1 and difference D = P1 - P0 (for f16 frames one
 //     mixed-precision FMA each).  New rows are prefetched a few rows ahead into
-//     registers; the previous frame's band stays in LDS (u8) or is read again,
-//     from the caches, through a second prefetch ring (f16), so HBM sees every
-//     frame once.
+//     registers; the previous frame's band stays in LDS in its packed form, so
+//     memory sees every frame once.
 //   * Rows are walked top to bottom.  Horizontal neighbour sums/differences of
 //     S and D give the derivative cube by one more vertical step.  Because the
 //     pyramid is linear, the 2x2 sums of S and D at even columns *are* the next
@@ -167,17 +166,10 @@ __device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&
   }
 }
 
-// Where the previous frame's band rows come from: u8 rows (8 bytes per lane)
-// are kept in LDS, each lane reading and writing only its own slots; f16 rows
-// (16 bytes per lane) would hold enough LDS to cap the waves per CU, so they are
-// read again from the caches through a second prefetch ring (the tuning sweep
-// measured each choice faster for its element type).
-template <typename T> constexpr bool kPrevInLds = sizeof(T) == 1;
-
-// The rows of a band are walked in groups of G = 4 rows (the depth of the
-// prefetch rings).  Rows walked: the band plus the halo of 2^(LV-1) rows below
-// it, rounded up to whole groups.
-template <int LV> constexpr int row_group() { return 4; }
+// The rows of a band are walked in groups of G rows (the depth of the prefetch
+// ring: 8 with four levels, else 4).  Rows walked: the band plus the halo of
+// 2^(LV-1) rows below it, rounded up to whole groups.
+template <int LV> constexpr int row_group() { return LV >= 4 ? 8 : 4; }
 template <int LV, int RH> constexpr int walked_rows() {
   return ((RH + (1 << (LV - 1))) + row_group<LV>() - 1) / row_group<LV>() * row_group<LV>();
 }
@@ -200,12 +192,10 @@ __device__ __forceinline__ void static_for(F&& f) {
 // vector-aligned; otherwise every walked row exists and the 8-pixel vector load
 // of a lane may run past column W into rows that exist.
 //
-// Rows of the current frame are prefetched G rows ahead through a register
-// ring that crosses frame boundaries: while the last rows of frame k are
-// processed, the first rows of frame k+1 are already in flight.  The previous
-// frame's rows are either the band store `prev` in LDS ([NR][64] packed rows)
-// or a second ring of the same kind; in the latter case they were read by this
-// wave one frame earlier and come back from the caches, not from HBM.
+// `prev` is this wave's LDS band store, [NR][64] packed rows of the previous
+// frame.  Rows of the current frame are prefetched G rows ahead through a
+// register ring that crosses frame boundaries: while the last rows of frame k
+// are processed, the first rows of frame k+1 are already in flight.
 template <typename T, int LV, int RH, bool CHECK>
 __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane, int lane, float* part,
                                           int64_t witem, Raw8<T>* prev, float* pbuf, float* red) {
@@ -257,19 +247,13 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
     }
   };
 
-  // the first group of frame 1 into the ring; the previous frame: frame 0
-  // into the band store (LDS) or its first group into the second ring
-  Raw8<T> ahead[G], ahead_prev[G];
-  if constexpr (kPrevInLds<T>) {
-    for (int w = 0; w < NR; ++w) {
-      Raw8<T> r;
-      load_row(r, band0, w);
-      prev[w * 64 + lane] = r;
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < G; ++i) load_row(ahead_prev[i], band0, i);
+  // frame 0 into the band store, the first group of frame 1 into the ring
+  for (int w = 0; w < NR; ++w) {
+    Raw8<T> r;
+    load_row(r, band0, w);
+    prev[w * 64 + lane] = r;
   }
+  Raw8<T> ahead[G];
 #pragma unroll
   for (int i = 0; i < G; ++i) load_row(ahead[i], band0 + fs_b, i);
 
@@ -297,23 +281,11 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
         constexpr int w = decltype(wc)::value;
         constexpr int i = w % G;
         const Raw8<T> cur = ahead[i];
-        Raw8<T> old;
-        if constexpr (kPrevInLds<T>) {
-          if constexpr (w + G < NR) load_row(ahead[i], fk, w + G);
-          else load_row(ahead[i], fnext, w + G - NR);
-          old = prev[w * 64 + lane];
-          prev[w * 64 + lane] = cur;
-        } else {
-          old = ahead_prev[i];
-          if constexpr (w + G < NR) {
-            load_row(ahead[i], fk, w + G);
-            load_row(ahead_prev[i], fk - fs_b, w + G);
-          } else {
-            load_row(ahead[i], fnext, w + G - NR);
-            load_row(ahead_prev[i], fnext - fs_b, w + G - NR);
-          }
-        }
+        if constexpr (w + G < NR) load_row(ahead[i], fk, w + G);
+        else load_row(ahead[i], fnext, w + G - NR);
         if (!CHECK || row0 + w < H) {
+          const Raw8<T> old = prev[w * 64 + lane];
+          prev[w * 64 + lane] = cur;
           float S[8], D[8];
           cur.sum_diff(old, S, D);
           float hs0[8], hd0[8], hD0[8];
@@ -443,7 +415,7 @@ __device__ __forceinline__ void band_walk(const SeqDesc& d, int row0, int c_lane
 template <typename T, int LV, int RH>
 __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
   constexpr int NR = walked_rows<LV, RH>();
-  __shared__ Raw8<T> prev[kPrevInLds<T> ? NR * 64 : 1];
+  __shared__ Raw8<T> prev[NR * 64];
   __shared__ float pbuf[kPartialChunk * LV * 10];
   __shared__ float red[8 * LV * 10];
   const int lane = threadIdx.x;

@@ -300,16 +300,15 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Built-in launch shape per (dtype, levels), from the tuning sweep of the fused
 // pass (paper_1612_08825_amd/autotune.py) on MI355X.
-// Sweep on MI355X (fused-pass ms; batched f16 workload at 4 levels, 64-stream
-// u8 mix at 3 levels): f16 best at 16 rows x 128 groups/CU (0.888 ms; 8 rows:
-// 0.926, 32 rows: 1.327), u8 best at 16 rows x 32 groups/CU (0.833 ms; 8 rows
-// x 64: 0.864).  More groups than items means one item per work-group,
-// dispatched by the hardware.
+// Sweep on MI355X (fused + finishing pass ms; batched f16 workload at 4 levels,
+// 64-stream u8 mix at 3 levels): f16 best at 8 rows x 64 groups/CU (16 and 32
+// rows hold too much LDS per wave), u8 best at 16 rows x 32 groups/CU.  More
+// groups than items means one item per work-group, dispatched by the hardware.
 tc_ttc_tuning default_tuning(int dtype, int levels) {
   (void)levels;
   tc_ttc_tuning t;
-  t.band_rows = 16;
-  t.groups_per_cu = dtype == TC_U8 ? 32 : 128;
+  t.band_rows = dtype == TC_U8 ? 16 : 8;
+  t.groups_per_cu = dtype == TC_U8 ? 32 : 64;
   return t;
 }
 

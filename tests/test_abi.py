@@ -183,7 +183,7 @@ def test_ttc_plan_validation(lib):
 def test_ttc_tuning_defaults_and_rejections(lib):
     t = L.TcTuning()
     assert lib.tc_ttc_tuning_default(L.TC_F16, 4, C.byref(t)) == 0
-    assert (t.band_rows, t.groups_per_cu) == (16, 128)
+    assert (t.band_rows, t.groups_per_cu) == (8, 64)
     assert lib.tc_ttc_tuning_default(L.TC_U8, 3, C.byref(t)) == 0
     assert (t.band_rows, t.groups_per_cu) == (16, 32)
     assert lib.tc_ttc_tuning_default(L.TC_F32, 3, C.byref(t)) == L.TC_EDTYPE
