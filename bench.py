@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20000.0, help="aggregate frame arrivals per second")
     ap.add_argument("--serve-budget-gib", type=float, default=2.0, help="device memory for stream state")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--conv-only", action="store_true",
+                    help="only the convolution sweep (with --profile: eager launches, no graph, for rocprofv3)")
     ap.add_argument("--save-frames", default=None, help="render the batch, save it to this .npz and exit")
     ap.add_argument("--load-frames", default=None, help="take the batch from a .npz written by --save-frames")
     return ap.parse_args()
@@ -102,9 +104,14 @@ def fused_work(specs, levels, es):
 
 
 # ----------------------------------------------------------------------------- CPU oracle leg
-def cpu_baseline(specs, budget_s):
+N_COMPARE = 16  # oracle results of the CPU leg that are compared with the GPU's
+
+
+def cpu_baseline(specs, budget_s, keep):
     """The oracle, as it stands, on frame pairs of the same workload until the
-    time budget is used (frame rendering is outside the timed part)."""
+    time budget is used (frame rendering is outside the timed part).  The frames
+    and oracle records of the first N_COMPARE pairs are appended to `keep`, so
+    that the GPU can solve the very same pairs afterwards."""
     import oracle as O
     from paper_1612_08825_amd import synth
 
@@ -120,8 +127,10 @@ def cpu_baseline(specs, budget_s):
         f0 = synth.render_frame(s.texture, s.H, s.W, s.foe, s.motion.m(3), s.dtype)
         f1 = synth.render_frame(s.texture, s.H, s.W, s.foe, s.motion.m(4), s.dtype)
         t0 = time.perf_counter()
-        O.ttc_pair(f0, f1, LEVELS)
+        recs = O.ttc_pair(f0, f1, LEVELS)
         el += time.perf_counter() - t0
+        if len(keep) < N_COMPARE:
+            keep.append((f0, f1, recs, O.select_level(recs)))
         px += s.H * s.W
         pairs += 1
         sizes.append(f"{s.W}x{s.H}")
@@ -137,7 +146,7 @@ def cpu_baseline(specs, budget_s):
 
 
 # ----------------------------------------------------------------------------- conv sweep
-def conv_sweep(api, torch, steps):
+def conv_sweep(api, torch, steps, use_graph=True):
     """Direct convolution, full mode, FP32; buffers rotated over >= 1 GiB so that
     the 256 MiB last-level cache cannot serve them.  Timed as a replayed graph of
     the launches (per-launch kernel time); the eager per-call time, which
@@ -171,6 +180,11 @@ def conv_sweep(api, torch, steps):
         e1.record()
         torch.cuda.synchronize()
         ms_eager = e0.elapsed_time(e1) / reps
+        if not use_graph:
+            out[f"{'x'.join(map(str, xs))}*{'x'.join(map(str, ks))}"] = {"ms_eager_calls": round(ms_eager, 5)}
+            del xbufs, ybufs
+            torch.cuda.empty_cache()
+            continue
         # the same launches captured once in a HIP graph: the host's per-call
         # cost drops out, what remains is the kernels back to back
         ref = ybufs[0].clone()
@@ -200,6 +214,64 @@ def conv_sweep(api, torch, steps):
         del xbufs, ybufs
         torch.cuda.empty_cache()
     return out
+
+
+# ----------------------------------------------------------------------------- accuracy
+def gpu_vs_oracle(api, torch, np, oracle_pairs):
+    """The CPU leg's pairs solved on the GPU (same frames, batched plan): the
+    largest differences from the FP64 oracle's records, per level and for the
+    multi-scale pick."""
+    if not oracle_pairs:
+        return None
+    vids = [torch.from_numpy(np.stack([f0, f1])).cuda() for f0, f1, _, _ in oracle_pairs]
+    worst = {"rel_C": 0.0, "rel_ttc": 0.0, "foe_px": 0.0, "rel_sum": 0.0}
+    same_pick = 0
+    status_equal = True
+    for v, (f0, f1, ref, sel) in zip(vids, oracle_pairs):
+        recs, picks = api.ttc_solve_batched([v], LEVELS)
+        for l in range(LEVELS):
+            g, r = recs[l], ref[l]
+            status_equal &= int(g["status"]) == int(r["status"])
+            worst["rel_sum"] = max(worst["rel_sum"], float(np.max(np.abs(g["sums"] - r["sums"])
+                                                                / np.maximum(np.abs(r["sums"]), 1e-300))))
+            if r["status"] == 0 and g["status"] == 0:
+                worst["rel_C"] = max(worst["rel_C"], abs(g["C"] - r["C"]) / abs(r["C"]))
+                worst["rel_ttc"] = max(worst["rel_ttc"], abs(g["ttc"] - r["ttc"]) / abs(r["ttc"]))
+                worst["foe_px"] = max(worst["foe_px"], abs(g["x0"] - r["x0"]), abs(g["y0"] - r["y0"]))
+        same_pick += int(picks[0]["level"]) == int(sel)
+    out = {k: float(f"{v:.3e}") for k, v in worst.items()}
+    out.update({"pairs": len(oracle_pairs), "levels": LEVELS, "status_equal": bool(status_equal),
+                "same_multiscale_level": f"{same_pick}/{len(oracle_pairs)}",
+                "note": "FP64 oracle records computed in the cpu_baseline leg on the same frames"})
+    return out
+
+
+def multiscale_mse(api, torch, np):
+    """The 300-frame 640x480 u8 approaching-plane video (FOE (+60, -40), TTC
+    falling linearly from 300 to 30 frames), 4 levels: mean squared error of
+    TTC and FOE against the analytic ground truth for every static level and
+    for the multi-scale choice, the paper's accuracy measure."""
+    from paper_1612_08825_amd import synth
+
+    v = synth.multiscale_video(device="cuda")
+    recs, picks = api.ttc_solve_batched([v.frames], LEVELS)
+    gt = v.ttc_gt()
+    foe = np.array(v.foe)
+    res = {}
+    for l in range(LEVELS):
+        r = recs[l::LEVELS]
+        ok = r["status"] == 0
+        res[f"level{l}"] = {"ttc_mse": float(np.mean((r["ttc"][ok] - gt[ok]) ** 2)),
+                            "foe_mse_px2": float(np.mean((r["x0"][ok] - foe[0]) ** 2 + (r["y0"][ok] - foe[1]) ** 2)),
+                            "ok_pairs": int(ok.sum())}
+    ok = picks["status"] == 0
+    res["multiscale"] = {"ttc_mse": float(np.mean((picks["ttc"][ok] - gt[ok]) ** 2)),
+                         "foe_mse_px2": float(np.mean((picks["x0"][ok] - foe[0]) ** 2
+                                                      + (picks["y0"][ok] - foe[1]) ** 2)),
+                         "ok_pairs": int(ok.sum()),
+                         "level_histogram": np.bincount(picks["level"][ok], minlength=LEVELS).tolist()}
+    res["pairs"] = int(len(picks))
+    return res
 
 
 # ----------------------------------------------------------------------------- plain path
@@ -316,7 +388,9 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported by this build "
               f"(streams shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
-    if args.profile:
+    if args.conv_only:
+        args.no_cpu = True
+    elif args.profile:
         args.no_cpu = True
         args.no_conv = True
 
@@ -324,8 +398,9 @@ def main():
 
     specs = synth.batched_specs()
     cpu = None
+    oracle_pairs = []
     if not args.no_cpu:  # before any GPU initialisation: the oracle leg is pure numpy
-        cpu = cpu_baseline(specs, args.cpu_seconds)
+        cpu = cpu_baseline(specs, args.cpu_seconds, oracle_pairs)
         print(f"[bench] cpu baseline done: {cpu['value']:.3e} Gpixel/s", file=sys.stderr, flush=True)
 
     import numpy as np
@@ -345,6 +420,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         torch.cuda.empty_cache()
+    if args.conv_only:
+        conv = conv_sweep(api, torch, max(10, args.steps), use_graph=not args.profile)
+        print(json.dumps({"conv_sweep": conv, "device": {"cus": n_cu}}), flush=True)
+        return
     if args.load_frames:
         # frames rendered earlier by --save-frames: this process launches no renderer kernels
         with np.load(args.load_frames, allow_pickle=False) as z:
@@ -447,6 +526,13 @@ def main():
     roof["alg_bytes"] = alg_bytes
     roof["alg_flops"] = flops
 
+    vs_oracle = None
+    ms_mse = None
+    if not args.profile:
+        vs_oracle = gpu_vs_oracle(api, torch, np, oracle_pairs)
+        ms_mse = multiscale_mse(api, torch, np)
+        print("[bench] accuracy done", file=sys.stderr, flush=True)
+
     plain = None
     if not args.no_plain and not args.profile:
         plain_ms, plain_lv, plain_pk = plain_path(api, torch, vids)
@@ -508,7 +594,8 @@ def main():
                   "Gpixel_per_s": None if graph_ms is None else round(pair_px / (graph_ms * 1e-3) / 1e9, 3),
                   "replays_match_eager": graph_ok},
         "deterministic_across_steps": deterministic,
-        "accuracy": {"ok_status_frac": ok_frac, "median_rel_err_vs_ground_truth": float(np.median(rel_err_sel))},
+        "accuracy": {"ok_status_frac": ok_frac, "median_rel_err_vs_ground_truth": float(np.median(rel_err_sel)),
+                     "vs_fp64_oracle": vs_oracle, "multiscale_video_mse": ms_mse},
         "cpu_baseline": cpu,
         "plain_one_pair_per_launch": plain,
         "serving": serve,
