@@ -147,7 +147,8 @@ def cpu_baseline(specs, budget_s, keep):
 
 # ----------------------------------------------------------------------------- conv sweep
 def conv_sweep(api, torch, steps, use_graph=True):
-    """Direct convolution, full mode, FP32; buffers rotated over >= 1 GiB so that
+    """Direct convolution (and the fused two-pass kernel on Gaussians), full mode,
+    FP32; buffers rotated over >= 1 GiB so that
     the 256 MiB last-level cache cannot serve them.  Timed as a replayed graph of
     the launches (per-launch kernel time); the eager per-call time, which
     includes the host's call overhead, is reported beside it."""
@@ -156,57 +157,72 @@ def conv_sweep(api, torch, steps, use_graph=True):
     from paper_1612_08825_amd import synth
 
     out = {}
-    cases = [(n, k) for n in (1024, 2048, 4096) for k in (3, 7, 15)] + [("3d", 3)]
-    for n, k in cases:
+    cases = [(n, k, False) for n in (1024, 2048, 4096) for k in (3, 7, 15)] + [("3d", 3, False)]
+    cases += [(4096, 7, True), (4096, 15, True), (2048, 15, True)]
+    for n, k, sep in cases:
         if n == "3d":
             xs, ks = (64, 256, 256), (3, 3, 3)
         else:
             xs, ks = (n, n), (k, k)
         x0 = torch.from_numpy(synth.conv_image(xs, case=7)).cuda()
-        kk = torch.from_numpy(synth.conv_kernel(ks, case=7)).cuda()
+        if sep:
+            # a Gaussian (sigma = K/6), applied through the fused two-pass kernel
+            t = np.arange(k) - (k - 1) / 2
+            g = np.exp(-t * t / (2 * (k / 6.0) ** 2))
+            g = torch.from_numpy((g / g.sum()).astype(np.float32)).cuda()
+            kk = None
+        else:
+            kk = torch.from_numpy(synth.conv_kernel(ks, case=7)).cuda()
+
+        def launch(i, xb, yb):
+            if sep:
+                api.conv_nd_separable(xb, g, g, "full", out=yb)
+            else:
+                api.conv_nd(xb, kk, "full", out=yb)
         ys = tuple(a + b - 1 for a, b in zip(xs, ks))
         nbytes = 4 * (math.prod(xs) + math.prod(ys))
         nbuf = max(2, min(64, int(math.ceil(1.1 * 2 ** 30 / nbytes))))
         xbufs = [x0.clone() for _ in range(nbuf)]
         ybufs = [torch.empty(ys, dtype=torch.float32, device="cuda") for _ in range(nbuf)]
         for i in range(3):
-            api.conv_nd(xbufs[i % nbuf], kk, "full", out=ybufs[i % nbuf])
+            launch(i, xbufs[i % nbuf], ybufs[i % nbuf])
         torch.cuda.synchronize()
         reps = max(steps, 2 * nbuf)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for i in range(reps):
-            api.conv_nd(xbufs[i % nbuf], kk, "full", out=ybufs[i % nbuf])
+            launch(i, xbufs[i % nbuf], ybufs[i % nbuf])
         e1.record()
         torch.cuda.synchronize()
         ms_eager = e0.elapsed_time(e1) / reps
+        name = f"{'x'.join(map(str, xs))}*{'x'.join(map(str, ks))}" + (" separable" if sep else "")
         if not use_graph:
-            out[f"{'x'.join(map(str, xs))}*{'x'.join(map(str, ks))}"] = {"ms_eager_calls": round(ms_eager, 5)}
+            out[name] = {"ms_eager_calls": round(ms_eager, 5)}
             del xbufs, ybufs
             torch.cuda.empty_cache()
             continue
         # the same launches captured once in a HIP graph: the host's per-call
         # cost drops out, what remains is the kernels back to back
         ref = ybufs[0].clone()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
             for i in range(reps):
-                api.conv_nd(xbufs[i % nbuf], kk, "full", out=ybufs[i % nbuf])
+                launch(i, xbufs[i % nbuf], ybufs[i % nbuf])
         ybufs[0].zero_()
-        g.replay()
+        graph.replay()
         torch.cuda.synchronize()
         same = bool(torch.equal(ybufs[0], ref))
         e0.record()
-        g.replay()
+        graph.replay()
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        del g
-        flops = 2.0 * math.prod(xs) * math.prod(ks)
+        del graph
+        # separable: 2K multiply-adds per output element instead of K^2 per input element
+        flops = 2.0 * math.prod(ys) * 2 * k if sep else 2.0 * math.prod(xs) * math.prod(ks)
         gbps = nbytes / (ms * 1e-3) / 1e9
         tf = flops / (ms * 1e-3) / 1e12
         bound = "hbm" if nbytes / (HBM_PEAK_GBPS * 1e9) >= flops / (ALU_PEAK_TFLOPS * 1e12) else "alu"
-        name = f"{'x'.join(map(str, xs))}*{'x'.join(map(str, ks))}"
         out[name] = {"ms": round(ms, 5), "ms_eager_calls": round(ms_eager, 5), "graph_matches_eager": same,
                      "Gelem_per_s": round(math.prod(xs) / (ms * 1e-3) / 1e9, 2),
                      "GB_per_s": round(gbps, 1), "TFLOP_per_s": round(tf, 2), "bound": bound,

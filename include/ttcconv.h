@@ -95,10 +95,35 @@ int tc_device_check(int device, int* n_cu);
  * with TC_EOVERFLOW unless 255 * sum|k| <= 2^31-1).  x and k have the same
  * rank 1..8.  x and y may be strided; k must be contiguous and at most
  * 2^20 elements, and is read from DEVICE memory.  y must not overlap x or k.
- * Float results are accumulated in FP32 in kernel-row-major tap order.
+ * Float results are accumulated in FP32 (the order of the taps is not
+ * specified).
  * ------------------------------------------------------------------------ */
 int tc_conv_out_shape(const tc_tensor* x, const tc_tensor* k, int32_t mode, int64_t* out_shape);
 int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Separable kernels
+ *
+ * Future Work section: a kernel that is the outer product of two vectors,
+ * k[a][b] = u[a] v[b] (directional derivatives, Gaussian smoothing, block
+ * averages), can be applied as two one-dimensional convolutions, 2K instead
+ * of K^2 multiply-adds per output.
+ *
+ * tc_conv_kernel_rank1: HOST arrays.  k is KH x KW, row-major.  Returns 1 and
+ * writes u[KH], v[KW] (FP32) when every |k[a][b] - u[a] v[b]| <= tol * max|k|
+ * (checked in double with the FP32 factors), 0 when k has no such
+ * factorisation (or holds a non-finite value), TC_EINVAL on bad arguments.
+ *
+ * tc_conv_nd_separable: y = x (*) (u v^T) with the modes and output extents of
+ * tc_conv_nd for a K x K kernel.  x and y are 2-D F32 with unit stride along
+ * their rows (the row stride is free); u and v are contiguous 1-D F32 of the
+ * same length K in {3, 5, 7, 9, 11, 15}, in DEVICE memory.  Both passes run
+ * in one kernel (no workspace, no intermediate image).  TC_EINVAL for other
+ * K, TC_ESHAPE / TC_EDTYPE as tc_conv_nd.
+ * ------------------------------------------------------------------------ */
+int tc_conv_kernel_rank1(const float* k, int32_t KH, int32_t KW, double tol, float* u, float* v);
+int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, const tc_tensor* v, int32_t mode,
+                         const tc_tensor* y, void* stream);
 
 /* ------------------------------------------------------------------------
  * Image pyramid

@@ -75,6 +75,9 @@ SIGNATURES = {
     "tc_version": (_I, []),
     "tc_device_check": (_I, [_I, C.POINTER(_I)]),
     "tc_conv_out_shape": (_I, [_T, _T, _I32, C.POINTER(_I64)]),
+    "tc_conv_kernel_rank1": (_I, [C.POINTER(C.c_float), _I32, _I32, C.c_double, C.POINTER(C.c_float),
+                                 C.POINTER(C.c_float)]),
+    "tc_conv_nd_separable": (_I, [_T, _T, _T, _I32, _T, _P]),
     "tc_conv_nd": (_I, [_T, _T, _I32, _T, _P]),
     "tc_pyramid_shape": (_I, [_I64, _I64, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
     "tc_image_pyramid": (_I, [_T, _I32, _T, _P]),

@@ -86,6 +86,54 @@ def conv_nd(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[
     return out
 
 
+def conv_kernel_rank1(k, tol: float = 2.0 ** -20):
+    """Host test of a 2-D kernel for separability: (True, u, v) with
+    k ~= outer(u, v) as FP32 numpy vectors, or (False, None, None)."""
+    kh = np.ascontiguousarray(k.detach().cpu().numpy() if isinstance(k, torch.Tensor) else k, dtype=np.float32)
+    if kh.ndim != 2:
+        raise ValueError("kernel must be 2-D")
+    u = np.empty(kh.shape[0], np.float32)
+    v = np.empty(kh.shape[1], np.float32)
+    fp = C.POINTER(C.c_float)
+    r = L.check("tc_conv_kernel_rank1",
+                _lib().tc_conv_kernel_rank1(kh.ctypes.data_as(fp), kh.shape[0], kh.shape[1], float(tol),
+                                            u.ctypes.data_as(fp), v.ctypes.data_as(fp)))
+    return (True, u, v) if r == 1 else (False, None, None)
+
+
+def conv_nd_separable(x: torch.Tensor, u: torch.Tensor, v: torch.Tensor, mode: str = "full",
+                      out: Optional[torch.Tensor] = None, stream=None):
+    """y = x (*) outer(u, v) for a 2-D FP32 image, both passes in one kernel."""
+    K = int(u.numel())
+    shape = conv_out_shape(tuple(x.shape), (K, K), mode, x.dtype, torch.float32)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device=x.device)
+    L.check("tc_conv_nd_separable",
+            _lib().tc_conv_nd_separable(C.byref(_desc(x)), C.byref(_desc(u)), C.byref(_desc(v)), L.MODES[mode],
+                                        C.byref(_desc(out)), _stream(stream)))
+    return out
+
+
+def conv_nd_auto(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[torch.Tensor] = None,
+                 stream=None, tol: float = 2.0 ** -20):
+    """conv_nd with separable-kernel detection: a 2-D FP32 kernel that is an
+    outer product (within tol * max|k|) and of a supported size runs as the
+    fused two-pass convolution, anything else as the direct one.  The kernel is
+    read back to the host once per call for the test."""
+    if (x.dim() == 2 and k.dim() == 2 and x.dtype == torch.float32 and k.dtype == torch.float32
+            and k.shape[0] == k.shape[1] and int(k.shape[0]) in SEPARABLE_SIZES and x.stride(1) == 1
+            and (out is None or out.stride(1) == 1)):
+        ok, u, v = conv_kernel_rank1(k, tol)
+        if ok:
+            uu = torch.from_numpy(u).to(x.device)
+            vv = torch.from_numpy(v).to(x.device)
+            return conv_nd_separable(x, uu, vv, mode, out, stream)
+    return conv_nd(x, k, mode, out, stream)
+
+
+SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
+
+
 # ----------------------------------------------------------------------------- pyramid / derivatives
 def image_pyramid(frame: torch.Tensor, levels: int, stream=None) -> List[torch.Tensor]:
     """[level 1, ..., level levels-1] as float32 tensors (level 0 is the frame itself)."""

@@ -579,6 +579,152 @@ hipError_t launch_roll_t(const RowArgs& ra, hipStream_t s) {
   }
 }
 
+// Separable kernels k[a][b] = u[a] v[b] (Future Work section: directional
+// derivatives, Gaussians, block averages).  The rolling-window walk of
+// conv2d_rows_roll with the two factors applied in turn: each input row is
+// first convolved along the row with v (K multiply-adds per output column),
+// then the K rows of the window take that row times u[a].  2K multiply-adds
+// per output instead of K^2, and no intermediate image.
+template <int K, int RB, int S>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void conv2d_rows_sep(RowArgs a,
+                                                                                             const float* uf,
+                                                                                             const float* vf) {
+  constexpr int NC = row_chunks<K, S>();
+  constexpr int LO = row_lanes_out<K, S>();
+  constexpr int NW = K + 3;
+  const int lane = threadIdx.x;
+  const int64_t G = gridDim.x, g = blockIdx.x;
+  const int64_t item = (G % 8 == 0) ? (g % 8) * (G / 8) + g / 8 : g;
+  if (item >= a.n_items) return;
+  const int band = (int)(item / a.n_cw);
+  const int cw = (int)(item - (int64_t)band * a.n_cw);
+  const int o0 = band * RB;
+  const int p_wave = cw * 4 * LO;
+  const int p_lane = p_wave + 4 * lane;
+  const int chunk0 = p_wave + a.off1 - (K - 1) - S;
+  const int cc = chunk0 + 4 * lane;
+  const bool chunk_in = cc >= 0 && cc + 4 <= a.W;
+  const uint32_t row_bytes = (uint32_t)a.W * 4u;
+  const int i0 = o0 + a.off0 - (K - 1);
+  const int n_out = RB < a.OH - o0 ? RB : a.OH - o0;
+  const int n_rows = n_out + K - 1;
+  const gptr<float> yp = as_global(a.y);
+  const bool store_lane = lane < LO;
+  const cptr<float> u = (cptr<float>)uf;
+  const cptr<float> v = (cptr<float>)vf;
+
+  auto load_chunk = [&](int row, float (&c4)[4]) {
+    if (row < 0 || row >= a.H) {  // uniform
+      c4[0] = c4[1] = c4[2] = c4[3] = 0.f;
+      return;
+    }
+    const float* rp = a.x + (int64_t)row * a.xs0;
+    if (chunk_in) {
+      const f4u q = *(const __attribute__((address_space(1))) f4u*)(rp + cc);
+      c4[0] = q.x;
+      c4[1] = q.y;
+      c4[2] = q.z;
+      c4[3] = q.w;
+    } else if (cc >= a.W || cc + 4 <= 0) {
+      c4[0] = c4[1] = c4[2] = c4[3] = 0.f;
+    } else {
+      const __amdgpu_buffer_rsrc_t rs = make_rsrc(rp, row_bytes);
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        c4[d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(cc + d) * 4u, 0, 0));
+    }
+  };
+
+  float acc[K][4];
+#pragma unroll
+  for (int t = 0; t < K; ++t)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[t][c] = 0.f;
+
+  float nxt[4];
+  load_chunk(i0, nxt);
+  for (int t = 0; t < n_rows; ++t) {
+    float ch[4 * NC];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ch[d] = nxt[d];
+    if (t + 1 < n_rows) load_chunk(i0 + t + 1, nxt);
+#pragma unroll
+    for (int k = 1; k < NC; ++k)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) ch[4 * k + d] = from_next_lane(ch[4 * (k - 1) + d]);
+    // the row pass: r[c] = sum_b v[b] x[row][col_c - b]
+    float r[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      const float vb = v[b];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) r[c] = fmaf(vb, ch[S + c + K - 1 - b], r[c]);
+    }
+    // the column pass: window row w (band output row t - (K - 1) + w) takes u[w]
+    const int w_lo = (K - 1 - t) > 0 ? K - 1 - t : 0;
+    const int w_hi = (n_out - 1) + (K - 1) - t;
+#pragma unroll
+    for (int w = 0; w < K; ++w) {
+      if (w < w_lo || w > w_hi) continue;
+      const float uw = u[w];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[w][c] = fmaf(uw, r[c], acc[w][c]);
+    }
+    const int j = t - (K - 1);
+    const int o = o0 + j;
+    if (j >= 0 && store_lane) {
+      const gptr<float> yr = yp + (int64_t)o * a.ys0 + p_lane;
+      if (p_lane + 3 < a.OW) {
+        f4u q;
+        q.x = acc[0][0];
+        q.y = acc[0][1];
+        q.z = acc[0][2];
+        q.w = acc[0][3];
+        *(__attribute__((address_space(1))) f4u*)yr = q;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (p_lane + c < a.OW) yr[c] = acc[0][c];
+      }
+    }
+#pragma unroll
+    for (int w = 0; w + 1 < K; ++w)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[w][c] = acc[w + 1][c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[K - 1][c] = 0.f;
+  }
+}
+
+template <int K, int RB, int S>
+hipError_t launch_sep_s(RowArgs ra, const float* u, const float* v, hipStream_t s) {
+  constexpr int LO = row_lanes_out<K, S>();
+  ra.n_bands = (ra.OH + RB - 1) / RB;
+  ra.n_cw = (ra.OW + 4 * LO - 1) / (4 * LO);
+  ra.n_items = (int64_t)ra.n_bands * ra.n_cw;
+  const int64_t grid = (ra.n_items + 7) / 8 * 8;
+  hipLaunchKernelGGL((conv2d_rows_sep<K, RB, S>), dim3((unsigned)grid), dim3(64), 0, s, ra, u, v);
+  return hipGetLastError();
+}
+
+template <int K, int RB>
+hipError_t launch_sep_rb(const RowArgs& ra, const float* u, const float* v, hipStream_t s) {
+  switch ((((ra.off1 - (K - 1)) % 4) + 4) % 4) {
+    case 0: return launch_sep_s<K, RB, 0>(ra, u, v, s);
+    case 1: return launch_sep_s<K, RB, 1>(ra, u, v, s);
+    case 2: return launch_sep_s<K, RB, 2>(ra, u, v, s);
+    default: return launch_sep_s<K, RB, 3>(ra, u, v, s);
+  }
+}
+
+template <int K>
+hipError_t launch_sep_k(const RowArgs& ra, const float* u, const float* v, hipStream_t s) {
+  constexpr int LO = row_lanes_out<K, 3>();
+  const int64_t items32 = (int64_t)((ra.OH + 31) / 32) * ((ra.OW + 4 * LO - 1) / (4 * LO));
+  if (items32 >= 2048) return launch_sep_rb<K, 32>(ra, u, v, s);
+  return launch_sep_rb<K, 8>(ra, u, v, s);
+}
+
 template <int KH, int KW, int R, int S>
 hipError_t launch_rows_s(RowArgs ra, hipStream_t s) {
   constexpr int LO = row_lanes_out<KW, S>();
@@ -630,7 +776,49 @@ hipError_t launch_rows(const RowArgs& ra, int KH, hipStream_t s) {
   }
 }
 
+__global__ __launch_bounds__(256) void fill_zero_words(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 }  // namespace
+
+bool separable_variant(int K) { return K == 3 || K == 5 || K == 7 || K == 9 || K == 11 || K == 15; }
+
+hipError_t launch_conv_separable(const SepConv& c, hipStream_t s) {
+  RowArgs ra{};
+  ra.x = c.x;
+  ra.xs0 = c.xs0;
+  ra.H = c.H;
+  ra.W = c.W;
+  ra.D = 1;
+  ra.KD = 1;
+  ra.y = c.y;
+  ra.ys0 = c.ys0;
+  ra.OH = c.OH;
+  ra.OW = c.OW;
+  ra.OD = 1;
+  ra.off0 = c.off0;
+  ra.off1 = c.off1;
+  switch (c.K) {
+    case 3: return launch_sep_k<3>(ra, c.u, c.v, s);
+    case 5: return launch_sep_k<5>(ra, c.u, c.v, s);
+    case 7: return launch_sep_k<7>(ra, c.u, c.v, s);
+    case 9: return launch_sep_k<9>(ra, c.u, c.v, s);
+    case 11: return launch_sep_k<11>(ra, c.u, c.v, s);
+    case 15: return launch_sep_k<15>(ra, c.u, c.v, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n = (int64_t)(bytes / 4);
+  if (n == 0) return hipSuccess;
+  const int64_t blocks64 = (n + 255) / 256;
+  const unsigned blocks = (unsigned)(blocks64 < 4096 ? blocks64 : 4096);
+  hipLaunchKernelGGL(fill_zero_words, dim3(blocks), dim3(256), 0, s, static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
 
 hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
   int64_t n_out = 1, n_taps = 1;

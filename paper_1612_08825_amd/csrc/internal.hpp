@@ -27,6 +27,25 @@ struct ConvND {
 // Chooses a kernel (2-D tiled, 3-D tiled, or generic rank-n) and launches it.
 hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s);
 
+// A 2-D FP32 convolution with a separable square kernel u v^T (K taps each).
+struct SepConv {
+  const float* x;
+  int64_t xs0;       // row stride (elements); unit stride along rows
+  int H, W;
+  const float* u;    // K taps along the columns (device)
+  const float* v;    // K taps along the rows (device)
+  int K;
+  float* y;
+  int64_t ys0;
+  int OH, OW;
+  int off0, off1;    // output index n maps to full index n + off
+};
+bool separable_variant(int K);
+hipError_t launch_conv_separable(const SepConv& c, hipStream_t s);
+
+// Zero `bytes` (a multiple of 4) of device memory with a kernel (graph-safe).
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
 // ---------------------------------------------------------------- pyramid / derivatives
 struct Image2D {
   const void* p;

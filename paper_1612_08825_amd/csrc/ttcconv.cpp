@@ -184,9 +184,10 @@ extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, 
     }
     if (255 * sabs > 2147483647LL) return TC_EOVERFLOW;
   }
-  // zero-size x: the result is all zeros in full/same mode
+  // zero-size x: the result is all zeros in full/same mode (a fill kernel, so
+  // that the call stays safe to record into a HIP graph)
   if (numel(x) == 0 || ktaps == 0) {
-    if (is_contiguous(y)) return hip_status(hipMemsetAsync(y->data, 0, (size_t)numel(y) * 4, s));
+    if (is_contiguous(y)) return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
     return TC_ESHAPE;
   }
 
@@ -205,6 +206,87 @@ extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, 
     c.off[d] = off[d];
   }
   return hip_status(launch_conv(c, small_taps, s));
+}
+
+// ============================================================================ separable kernels
+extern "C" int tc_conv_kernel_rank1(const float* k, int32_t KH, int32_t KW, double tol, float* u, float* v) {
+  if (!k || !u || !v || KH < 1 || KW < 1 || KH > 4096 || KW > 4096 || !(tol >= 0.0)) return TC_EINVAL;
+  // pivot: the entry of largest magnitude; u = its column, v = its row over it
+  int p = 0, q = 0;
+  double kmax = 0.0;
+  for (int a = 0; a < KH; ++a)
+    for (int b = 0; b < KW; ++b) {
+      const double m = std::fabs((double)k[(size_t)a * KW + b]);
+      if (!(m <= kmax)) {
+        if (!std::isfinite(m)) return 0;
+        kmax = m;
+        p = a;
+        q = b;
+      }
+    }
+  if (kmax == 0.0) {
+    for (int a = 0; a < KH; ++a) u[a] = 0.f;
+    for (int b = 0; b < KW; ++b) v[b] = 0.f;
+    return 1;
+  }
+  const double piv = (double)k[(size_t)p * KW + q];
+  const double sc = std::sqrt(std::fabs(piv));  // balance the two factors' magnitudes
+  for (int a = 0; a < KH; ++a) u[a] = (float)((double)k[(size_t)a * KW + q] / sc);
+  for (int b = 0; b < KW; ++b) v[b] = (float)((double)k[(size_t)p * KW + b] * sc / piv);
+  for (int a = 0; a < KH; ++a)
+    for (int b = 0; b < KW; ++b)
+      if (std::fabs((double)k[(size_t)a * KW + b] - (double)u[a] * (double)v[b]) > tol * kmax) return 0;
+  return 1;
+}
+
+extern "C" int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, const tc_tensor* v, int32_t mode,
+                                    const tc_tensor* y, void* stream) {
+  int st;
+  if ((st = check_tensor(x, true)) != TC_OK) return st;
+  if ((st = check_tensor(u, true)) != TC_OK) return st;
+  if ((st = check_tensor(v, true)) != TC_OK) return st;
+  if ((st = check_tensor(y, true)) != TC_OK) return st;
+  if (x->dtype != TC_F32 || u->dtype != TC_F32 || v->dtype != TC_F32 || y->dtype != TC_F32) return TC_EDTYPE;
+  if (x->ndim != 2 || y->ndim != 2 || u->ndim != 1 || v->ndim != 1) return TC_ESHAPE;
+  if (!is_contiguous(u) || !is_contiguous(v) || u->shape[0] != v->shape[0]) return TC_ESHAPE;
+  const int K = (int)u->shape[0];
+  if (!separable_variant(K)) return TC_EINVAL;
+  if (x->stride[1] != 1 || y->stride[1] != 1) return TC_ESHAPE;
+  // the geometry of the equivalent K x K kernel
+  tc_tensor kv{};
+  kv.data = u->data;
+  kv.dtype = TC_F32;
+  kv.ndim = 2;
+  kv.shape[0] = K;
+  kv.shape[1] = K;
+  kv.stride[0] = K;
+  kv.stride[1] = 1;
+  int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
+  if ((st = conv_geometry(x, &kv, mode, oshape, off)) != TC_OK) return st;
+  if (y->shape[0] != oshape[0] || y->shape[1] != oshape[1]) return TC_ESHAPE;
+  if (numel(y) == 0) return TC_OK;
+  for (int d = 0; d < 2; ++d)
+    if (x->shape[d] >= (1LL << 28) || y->shape[d] >= (1LL << 28) || off[d] >= (1LL << 28)) return TC_EINVAL;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (numel(x) == 0) {
+    if (y->stride[0] == y->shape[1]) return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
+    return TC_ESHAPE;
+  }
+  SepConv c{};
+  c.x = static_cast<const float*>(x->data);
+  c.xs0 = x->stride[0];
+  c.H = (int)x->shape[0];
+  c.W = (int)x->shape[1];
+  c.u = static_cast<const float*>(u->data);
+  c.v = static_cast<const float*>(v->data);
+  c.K = K;
+  c.y = static_cast<float*>(y->data);
+  c.ys0 = y->stride[0];
+  c.OH = (int)y->shape[0];
+  c.OW = (int)y->shape[1];
+  c.off0 = (int)off[0];
+  c.off1 = (int)off[1];
+  return hip_status(launch_conv_separable(c, s));
 }
 
 // ============================================================================ pyramid / derivatives
