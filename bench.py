@@ -232,6 +232,51 @@ def conv_sweep(api, torch, steps, use_graph=True):
     return out
 
 
+def gradient_sweep(api, torch, steps):
+    """tc_gradient on 4096 x 4096 images (every output: E_x, E_y, magnitude,
+    direction), buffers rotated over >= 1 GiB, timed as a replayed graph."""
+    import numpy as np
+
+    out = {}
+    n = 4096
+    rng = np.random.default_rng(11)
+    for dt, stencil in (("u8", "fd2"), ("u8", "sobel3"), ("f32", "sobel3")):
+        if dt == "u8":
+            x0 = torch.from_numpy(rng.integers(0, 256, (n, n), dtype=np.uint8)).cuda()
+        else:
+            x0 = torch.from_numpy(rng.uniform(0, 1, (n, n)).astype(np.float32)).cuda()
+        k = 3 if stencil == "sobel3" else 2
+        m = n - k + 1
+        nbytes = x0.element_size() * n * n + 16 * m * m
+        nbuf = max(2, min(32, int(math.ceil(1.1 * 2 ** 30 / nbytes))))
+        xb = [x0.clone() for _ in range(nbuf)]
+        ob = [{q: torch.empty((m, m), device="cuda") for q in ("ex", "ey", "mag", "dir")} for _ in range(nbuf)]
+        for i in range(3):
+            api.gradient(xb[i % nbuf], stencil, out=ob[i % nbuf])
+        torch.cuda.synchronize()
+        reps = max(steps, 2 * nbuf)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for i in range(reps):
+                api.gradient(xb[i % nbuf], stencil, out=ob[i % nbuf])
+        graph.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        del graph
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        out[f"{n}x{n} {dt} {stencil}"] = {"ms": round(ms, 5), "Gpixel_per_s": round(m * m / (ms * 1e-3) / 1e9, 2),
+                                          "GB_per_s": round(gbps, 1), "bound": "hbm",
+                                          "frac": round(gbps / HBM_PEAK_GBPS, 3)}
+        del xb, ob
+        torch.cuda.empty_cache()
+    return out
+
+
 # ----------------------------------------------------------------------------- accuracy
 def gpu_vs_oracle(api, torch, np, oracle_pairs):
     """The CPU leg's pairs solved on the GPU (same frames, batched plan): the
@@ -270,7 +315,13 @@ def multiscale_mse(api, torch, np):
     from paper_1612_08825_amd import synth
 
     v = synth.multiscale_video(device="cuda")
-    recs, picks = api.ttc_solve_batched([v.frames], LEVELS)
+    plan = api.TTCPlan([api.seq_from_frames(v.frames, LEVELS)], v.frames.dtype, keep=[v.frames])
+    plan.run()
+    resel = api.ttc_reselect(plan.levels_buf, plan.n_pairs, LEVELS, "min_residual")
+    torch.cuda.synchronize()
+    recs, picks = plan.results()
+    picks_resid = api.decode_picks(resel[: plan.n_pairs * 56])
+    plan.close()
     gt = v.ttc_gt()
     foe = np.array(v.foe)
     res = {}
@@ -280,12 +331,12 @@ def multiscale_mse(api, torch, np):
         res[f"level{l}"] = {"ttc_mse": float(np.mean((r["ttc"][ok] - gt[ok]) ** 2)),
                             "foe_mse_px2": float(np.mean((r["x0"][ok] - foe[0]) ** 2 + (r["y0"][ok] - foe[1]) ** 2)),
                             "ok_pairs": int(ok.sum())}
-    ok = picks["status"] == 0
-    res["multiscale"] = {"ttc_mse": float(np.mean((picks["ttc"][ok] - gt[ok]) ** 2)),
-                         "foe_mse_px2": float(np.mean((picks["x0"][ok] - foe[0]) ** 2
-                                                      + (picks["y0"][ok] - foe[1]) ** 2)),
-                         "ok_pairs": int(ok.sum()),
-                         "level_histogram": np.bincount(picks["level"][ok], minlength=LEVELS).tolist()}
+    for name, pk in (("multiscale", picks), ("multiscale_min_residual", picks_resid)):
+        ok = pk["status"] == 0
+        res[name] = {"ttc_mse": float(np.mean((pk["ttc"][ok] - gt[ok]) ** 2)),
+                     "foe_mse_px2": float(np.mean((pk["x0"][ok] - foe[0]) ** 2 + (pk["y0"][ok] - foe[1]) ** 2)),
+                     "ok_pairs": int(ok.sum()),
+                     "level_histogram": np.bincount(pk["level"][ok], minlength=LEVELS).tolist()}
     res["pairs"] = int(len(picks))
     return res
 
@@ -438,7 +489,8 @@ def main():
         torch.cuda.empty_cache()
     if args.conv_only:
         conv = conv_sweep(api, torch, max(10, args.steps), use_graph=not args.profile)
-        print(json.dumps({"conv_sweep": conv, "device": {"cus": n_cu}}), flush=True)
+        grad = gradient_sweep(api, torch, max(10, args.steps))
+        print(json.dumps({"conv_sweep": conv, "gradient_sweep": grad, "device": {"cus": n_cu}}), flush=True)
         return
     if args.load_frames:
         # frames rendered earlier by --save-frames: this process launches no renderer kernels
@@ -564,10 +616,12 @@ def main():
         del plain_lv, plain_pk
         print(f"[bench] plain path done: {plain['Gpixel_per_s']} Gpixel/s", file=sys.stderr, flush=True)
 
-    conv = None
+    conv = grad = None
     if not args.no_conv:
         conv = conv_sweep(api, torch, max(10, args.steps))
         print("[bench] conv sweep done", file=sys.stderr, flush=True)
+        grad = gradient_sweep(api, torch, max(10, args.steps))
+        print("[bench] gradient sweep done", file=sys.stderr, flush=True)
 
     serve = None
     if not args.no_serve and not args.profile:
@@ -616,6 +670,7 @@ def main():
         "plain_one_pair_per_launch": plain,
         "serving": serve,
         "conv_sweep": conv,
+        "gradient_sweep": grad,
         "device": {"cus": n_cu, "name": torch.cuda.get_device_name(0)},
     }
     print(json.dumps(line), flush=True)

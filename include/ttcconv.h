@@ -162,6 +162,34 @@ int tc_horn_derivs(const tc_tensor* prev, const tc_tensor* next, const tc_tensor
                    const tc_tensor* et, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Image gradient, magnitude and direction
+ *
+ * Discrete Derivatives section: the gradient's magnitude |E| = sqrt(E_x^2 +
+ * E_y^2) and its direction, the four-quadrant inverse tangent of (E_y, E_x)
+ * in [-pi, pi], at every position of a mask; Convolutions section: the masks.
+ * The figure that gives the masks is missing from the text, so they take their
+ * textbook coefficients, scaled so that the ramp E = x has E_x = 1:
+ *   TC_STENCIL_FD2       (1/2)[[-1, 1], [-1, 1]] and its transpose (the
+ *                        Discrete Derivatives mask; 2x2 Prewitt)
+ *   TC_STENCIL_ROBERTS   E(i+1,j+1) - E(i,j) and E(i+1,j) - E(i,j+1), / sqrt(2)
+ *                        (axes turned by 45 degrees)
+ *   TC_STENCIL_PREWITT3  rows [-1, 0, 1] / 6 and the transpose
+ *   TC_STENCIL_SOBEL3    rows [-1, 0, 1] weighted 1, 2, 1, / 8, and the transpose
+ * Masks are applied as written (no flip) where they fit: outputs are
+ * (H-1) x (W-1) for the 2x2 masks and (H-2) x (W-2) for the 3x3 ones, x = column.
+ * `image` is a 2-D U8, F16 or F32 image (strided); ex, ey, mag, dir are 2-D
+ * F32 tensors of the output extent, each optional (NULL descriptor or NULL
+ * data: not computed).  Computed in FP32 (integer mask weights summed first,
+ * one scale).
+ * ------------------------------------------------------------------------ */
+#define TC_STENCIL_FD2 0
+#define TC_STENCIL_ROBERTS 1
+#define TC_STENCIL_PREWITT3 2
+#define TC_STENCIL_SOBEL3 3
+int tc_gradient(const tc_tensor* image, int32_t stencil, const tc_tensor* ex, const tc_tensor* ey,
+                const tc_tensor* mag, const tc_tensor* dir, void* stream);
+
+/* ------------------------------------------------------------------------
  * Time to contact and focus of expansion
  *
  * Time to Contact, Formulation: with the radial gradient G = x E_x + y E_y,
@@ -286,6 +314,20 @@ int tc_ttc_plan_run_phase(const tc_ttc_plan* plan, void* ws, size_t ws_bytes, tc
                           tc_ttc_pick* picks_out, int32_t phase, void* stream);
 /* Frees the plan (synchronises the device first). */
 void tc_ttc_plan_destroy(tc_ttc_plan* plan);
+
+/* The multi-scale choice re-applied to level records already in device
+ * memory (levels_out of a run: n_pairs x levels records, pair-major) into
+ * picks_out[n_pairs].  TC_SELECT_DECREASING_TTC is the Results subsection's
+ * rule as every run applies it (descend while the TTC estimate keeps
+ * decreasing); TC_SELECT_MIN_RESIDUAL reads "improved" as a better fit: the
+ * level with a valid TTC and the smallest residual per cube (resid / n), the
+ * lower level on a tie, level 0 when none is valid.  levels_per_pair is 1..16
+ * (TC_EINVAL otherwise, or for another rule); both arrays are device memory
+ * owned by the caller.  Launches only (no allocation, no synchronisation). */
+#define TC_SELECT_DECREASING_TTC 0
+#define TC_SELECT_MIN_RESIDUAL 1
+int tc_ttc_reselect(const tc_ttc_level* levels, int64_t n_pairs, int32_t levels_per_pair, int32_t rule,
+                    tc_ttc_pick* picks_out, void* stream);
 
 /* Create + upload + run + stream synchronise + destroy, for one-off calls. */
 int tc_ttc_solve_batched(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, void* ws, size_t ws_bytes,

@@ -18,6 +18,8 @@ Modules:
               the 2x2 derivative kernel, extended over two frames)
   ttc      -- radial gradient, least-squares normal equations, 3x3 solve,
               FOE / TTC, multi-scale level selection (Time to Contact)
+  gradient -- image gradient with the 2x2 / 3x3 masks, its magnitude and
+              direction (Discrete Derivatives; Convolutions)
 """
 from .conv import conv, conv_full, conv_at, conv_bruteforce, conv_out_shape  # noqa: F401
 from .pyramid import pyramid, reduce2  # noqa: F401
@@ -36,5 +38,7 @@ from .ttc import (  # noqa: F401
     solve_level,
     ttc_pair,
     select_level,
+    select_level_residual,
     ttc_sequence,
 )
+from .gradient import STENCILS, apply_mask, gradient, masks  # noqa: F401

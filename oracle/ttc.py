@@ -205,6 +205,22 @@ def select_level(results: Sequence[Dict]) -> int:
     return l
 
 
+def select_level_residual(results: Sequence[Dict]) -> int:
+    """The other reading of the multi-scale rule (Results subsection: "improved"
+    read as a better fit): the level whose solution violates the constraint
+    least on average, i.e. the smallest residual / number of cubes, among the
+    levels with a valid (finite, positive) TTC; the lower level on a tie;
+    level 0 when no level is valid."""
+    best, best_val = 0, math.inf
+    for l, r in enumerate(results):
+        if _key(r) == math.inf or r["n"] <= 0:
+            continue
+        v = r["resid"] / r["n"]
+        if v < best_val:
+            best, best_val = l, v
+    return best
+
+
 def ttc_sequence(frames, levels: int = 1):
     """[(per-level results, selected level)] for every consecutive pair of a [F, H, W] video."""
     out = []

@@ -23,6 +23,8 @@ TC_NUM_SUMS = 10
 
 MODES = {"full": TC_FULL, "same": TC_SAME, "valid": TC_VALID}
 TC_PHASE_FUSED, TC_PHASE_FINISH = 1, 2
+TC_STENCIL_FD2, TC_STENCIL_ROBERTS, TC_STENCIL_PREWITT3, TC_STENCIL_SOBEL3 = 0, 1, 2, 3
+TC_SELECT_DECREASING_TTC, TC_SELECT_MIN_RESIDUAL = 0, 1
 
 
 class TcTensor(C.Structure):
@@ -82,6 +84,8 @@ SIGNATURES = {
     "tc_pyramid_shape": (_I, [_I64, _I64, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
     "tc_image_pyramid": (_I, [_T, _I32, _T, _P]),
     "tc_horn_derivs": (_I, [_T, _T, _T, _T, _T, _P]),
+    "tc_gradient": (_I, [_T, _I32, _T, _T, _T, _T, _P]),
+    "tc_ttc_reselect": (_I, [_P, _I64, _I32, _I32, _P, _P]),
     "tc_ttc_plan_create": (_I, [C.POINTER(TcSeq), _I32, _I32, C.POINTER(_P)]),
     "tc_ttc_tuning_default": (_I, [_I32, _I32, C.POINTER(TcTuning)]),
     "tc_ttc_plan_create_ex": (_I, [C.POINTER(TcSeq), _I32, _I32, C.POINTER(TcTuning), C.POINTER(_P)]),

@@ -156,7 +156,46 @@ def horn_derivs(prev: torch.Tensor, nxt: torch.Tensor, exact_int: bool = False, 
     return tuple(outs)
 
 
+STENCILS = {"fd2": L.TC_STENCIL_FD2, "roberts": L.TC_STENCIL_ROBERTS, "prewitt3": L.TC_STENCIL_PREWITT3,
+            "sobel3": L.TC_STENCIL_SOBEL3}
+
+
+def gradient(image: torch.Tensor, stencil: str = "fd2", want=("ex", "ey", "mag", "dir"), out=None, stream=None):
+    """Gradient (E_x, E_y), magnitude and direction of a 2-D image under one of
+    the masks of ``STENCILS``: a dict of the FP32 outputs asked for in ``want``
+    (or the tensors given in ``out``, a dict by the same names), each
+    (H-k+1) x (W-k+1) for a k x k mask."""
+    lib = _lib()
+    st = STENCILS[stencil]
+    k = 3 if st >= L.TC_STENCIL_PREWITT3 else 2
+    H, W = image.shape
+    shape = (max(H - k + 1, 0), max(W - k + 1, 0))
+    outs = dict(out) if out is not None else \
+        {n: torch.empty(shape, dtype=torch.float32, device=image.device) for n in want}
+    ds = [C.byref(_desc(outs[n])) if n in outs else None for n in ("ex", "ey", "mag", "dir")]
+    L.check("tc_gradient", lib.tc_gradient(C.byref(_desc(image)), st, *ds, _stream(stream)))
+    return outs
+
+
 # ----------------------------------------------------------------------------- time to contact
+SELECT_RULES = {"decreasing_ttc": L.TC_SELECT_DECREASING_TTC, "min_residual": L.TC_SELECT_MIN_RESIDUAL}
+
+
+def ttc_reselect(levels_buf: torch.Tensor, n_pairs: int, levels: int, rule: str = "min_residual",
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The multi-scale choice re-applied to device level records (n_pairs x
+    levels records, pair-major) by ``rule``: a device buffer of n_pairs picks."""
+    if levels_buf.numel() < n_pairs * levels * L.LEVEL_DTYPE.itemsize:
+        raise ValueError("level buffer smaller than n_pairs x levels records")
+    if out is None:
+        out = torch.empty(max(n_pairs, 1) * L.PICK_DTYPE.itemsize, dtype=torch.uint8, device=levels_buf.device)
+    elif out.numel() < n_pairs * L.PICK_DTYPE.itemsize:
+        raise ValueError("pick buffer smaller than n_pairs picks")
+    L.check("tc_ttc_reselect", _lib().tc_ttc_reselect(C.c_void_p(levels_buf.data_ptr()), n_pairs, levels,
+                                                       SELECT_RULES[rule], C.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
 def decode_levels(buf: torch.Tensor) -> np.ndarray:
     """tc_ttc_level records (device bytes) -> numpy structured array."""
     return buf.cpu().numpy().view(L.LEVEL_DTYPE)

@@ -46,6 +46,14 @@ hipError_t launch_conv_separable(const SepConv& c, hipStream_t s);
 // Zero `bytes` (a multiple of 4) of device memory with a kernel (graph-safe).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
+// ---------------------------------------------------------------- gradient
+struct GradOut {
+  float* ex;  int64_t ex0, ex1;  // each output may be null (not written)
+  float* ey;  int64_t ey0, ey1;
+  float* mag; int64_t mag0, mag1;
+  float* dir; int64_t dir0, dir1;
+};
+
 // ---------------------------------------------------------------- pyramid / derivatives
 struct Image2D {
   const void* p;
@@ -53,6 +61,7 @@ struct Image2D {
   int64_t s0, s1;  // strides (elements)
 };
 
+hipError_t launch_gradient(const Image2D& src, int stencil, int Ho, int Wo, const GradOut& o, hipStream_t s);
 hipError_t launch_pyramid_level(const Image2D& src, float* dst, int64_t d0, int64_t d1, int Ho, int Wo,
                                 hipStream_t s);
 hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, void* ex, void* ey, void* et,
@@ -103,5 +112,7 @@ struct FusedLaunch {
 hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s);
 hipError_t launch_ttc_finish(const FusedLaunch& f, tc_ttc_level* out, tc_ttc_pick* picks, hipStream_t s);
 bool fused_variant_exists(int dt, int levels, int band_rows);
+hipError_t launch_ttc_reselect(const tc_ttc_level* levels, int64_t n_pairs, int L, int rule, tc_ttc_pick* picks,
+                              hipStream_t s);
 
 }  // namespace ttc

@@ -58,6 +58,63 @@ __global__ __launch_bounds__(256) void horn_cube(const T* __restrict__ p0, int64
   }
 }
 
+// Gradient of one image with a 2x2 or 3x3 mask (the mask's integer weights
+// summed first, then one scale), its magnitude sqrt(ex^2 + ey^2) and its
+// four-quadrant direction atan2(ey, ex).  One thread per output pixel; an
+// output whose pointer is null is not written.
+//   ST 0 fd2      (1/2)[[-1, 1], [-1, 1]] and its transpose
+//   ST 1 roberts  diagonal differences (x: (i+1,j+1) - (i,j); y: (i+1,j) - (i,j+1)) / sqrt(2)
+//   ST 2 prewitt3 rows [-1, 0, 1] / 6 and the transpose
+//   ST 3 sobel3   rows [-1, 0, 1] weighted 1, 2, 1, / 8, and the transpose
+template <typename T, int ST>
+__global__ __launch_bounds__(256) void gradient_kernel(const T* __restrict__ src, int64_t s0, int64_t s1, int Ho,
+                                                        int Wo, float* __restrict__ ex, int64_t e0, int64_t e1,
+                                                        float* __restrict__ ey, int64_t f0, int64_t f1,
+                                                        float* __restrict__ mag, int64_t m0, int64_t m1,
+                                                        float* __restrict__ dir, int64_t g0, int64_t g1) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= Wo) return;
+  auto p = [&](int r, int c) -> float { return to_f32<T>(src[(int64_t)(i + r) * s0 + (int64_t)(j + c) * s1]); };
+  float gx, gy;
+  if constexpr (ST == 0) {
+    gx = ((p(0, 1) - p(0, 0)) + (p(1, 1) - p(1, 0))) * 0.5f;
+    gy = ((p(1, 0) - p(0, 0)) + (p(1, 1) - p(0, 1))) * 0.5f;
+  } else if constexpr (ST == 1) {
+    constexpr float r = 0.70710678118654752f;
+    gx = (p(1, 1) - p(0, 0)) * r;
+    gy = (p(1, 0) - p(0, 1)) * r;
+  } else {
+    constexpr float w1 = ST == 2 ? 1.f : 2.f;
+    constexpr float sc = ST == 2 ? 1.f / 6.f : 0.125f;
+    gx = ((p(0, 2) - p(0, 0)) + w1 * (p(1, 2) - p(1, 0)) + (p(2, 2) - p(2, 0))) * sc;
+    gy = ((p(2, 0) - p(0, 0)) + w1 * (p(2, 1) - p(0, 1)) + (p(2, 2) - p(0, 2))) * sc;
+  }
+  if (ex) ex[(int64_t)i * e0 + (int64_t)j * e1] = gx;
+  if (ey) ey[(int64_t)i * f0 + (int64_t)j * f1] = gy;
+  if (mag) mag[(int64_t)i * m0 + (int64_t)j * m1] = sqrtf(gx * gx + gy * gy);
+  if (dir) dir[(int64_t)i * g0 + (int64_t)j * g1] = atan2f(gy, gx);
+}
+
+template <typename T, int ST>
+hipError_t gradient_ts(const Image2D& src, int Ho, int Wo, const GradOut& o, hipStream_t st) {
+  const dim3 block(256), grid((unsigned)((Wo + 255) / 256), (unsigned)Ho);
+  hipLaunchKernelGGL((gradient_kernel<T, ST>), grid, block, 0, st, static_cast<const T*>(src.p), src.s0, src.s1, Ho,
+                     Wo, o.ex, o.ex0, o.ex1, o.ey, o.ey0, o.ey1, o.mag, o.mag0, o.mag1, o.dir, o.dir0, o.dir1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gradient_t(const Image2D& src, int stencil, int Ho, int Wo, const GradOut& o, hipStream_t st) {
+  switch (stencil) {
+    case TC_STENCIL_FD2: return gradient_ts<T, 0>(src, Ho, Wo, o, st);
+    case TC_STENCIL_ROBERTS: return gradient_ts<T, 1>(src, Ho, Wo, o, st);
+    case TC_STENCIL_PREWITT3: return gradient_ts<T, 2>(src, Ho, Wo, o, st);
+    case TC_STENCIL_SOBEL3: return gradient_ts<T, 3>(src, Ho, Wo, o, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 hipError_t pyr_t(const Image2D& s, float* dst, int64_t d0, int64_t d1, int Ho, int Wo, hipStream_t st) {
   const dim3 grid((unsigned)((Wo + 255) / 256), (unsigned)Ho);
@@ -100,6 +157,16 @@ hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, v
     case TC_U8: return horn_t<uint8_t, float>(prev, next, H, W, ex, ey, et, os0, os1, s);
     case TC_F16: return horn_t<_Float16, float>(prev, next, H, W, ex, ey, et, os0, os1, s);
     case TC_F32: return horn_t<float, float>(prev, next, H, W, ex, ey, et, os0, os1, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_gradient(const Image2D& src, int stencil, int Ho, int Wo, const GradOut& o, hipStream_t s) {
+  if (Ho <= 0 || Wo <= 0) return hipSuccess;
+  switch (src.dt) {
+    case TC_U8: return gradient_t<uint8_t>(src, stencil, Ho, Wo, o, s);
+    case TC_F16: return gradient_t<_Float16>(src, stencil, Ho, Wo, o, s);
+    case TC_F32: return gradient_t<float>(src, stencil, Ho, Wo, o, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -529,6 +529,41 @@ __device__ __forceinline__ double level_key(const tc_ttc_level& r) {
   return r.ttc;
 }
 
+// The multi-scale choice again, from level records already in device memory:
+// rule 0 descends while the TTC keeps decreasing (as ttc_finish does), rule 1
+// takes the valid level with the smallest residual per cube (the lower level
+// on a tie; level 0 when none is valid).  One thread per pair.
+__global__ __launch_bounds__(256) void ttc_reselect(const tc_ttc_level* __restrict__ lv, int64_t n_pairs, int L,
+                                                    int rule, tc_ttc_pick* __restrict__ picks) {
+  const int64_t gp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gp >= n_pairs) return;
+  const tc_ttc_level* r = lv + gp * L;
+  int l = 0;
+  if (rule == TC_SELECT_DECREASING_TTC) {
+    while (l + 1 < L && level_key(r[l + 1]) < level_key(r[l])) ++l;
+  } else {
+    double best = __builtin_inf();
+    for (int k = 0; k < L; ++k) {
+      if (!(level_key(r[k]) < __builtin_inf()) || r[k].n <= 0) continue;
+      const double v = r[k].resid / (double)r[k].n;
+      if (v < best) {
+        best = v;
+        l = k;
+      }
+    }
+  }
+  tc_ttc_pick pk;
+  pk.ttc = r[l].ttc;
+  pk.x0 = r[l].x0;
+  pk.y0 = r[l].y0;
+  pk.A = r[l].A;
+  pk.B = r[l].B;
+  pk.C = r[l].C;
+  pk.level = l;
+  pk.status = r[l].status;
+  picks[gp] = pk;
+}
+
 template <int LV>
 __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __restrict__ out,
                                                   tc_ttc_pick* __restrict__ picks) {
@@ -647,6 +682,14 @@ hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s) {
     case TC_F16: return fused_lv<_Float16>(f, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_ttc_reselect(const tc_ttc_level* levels, int64_t n_pairs, int L, int rule, tc_ttc_pick* picks,
+                              hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n_pairs + 255) / 256)), block(256);
+  hipLaunchKernelGGL(ttc_reselect, grid, block, 0, s, levels, n_pairs, L, rule, picks);
+  return hipGetLastError();
 }
 
 hipError_t launch_ttc_finish(const FusedLaunch& f, tc_ttc_level* out, tc_ttc_pick* picks, hipStream_t s) {

@@ -356,6 +356,50 @@ extern "C" int tc_horn_derivs(const tc_tensor* prev, const tc_tensor* next, cons
                                 reinterpret_cast<hipStream_t>(stream)));
 }
 
+extern "C" int tc_gradient(const tc_tensor* image, int32_t stencil, const tc_tensor* ex, const tc_tensor* ey,
+                           const tc_tensor* mag, const tc_tensor* dir, void* stream) {
+  int st;
+  if ((st = check_tensor(image, true)) != TC_OK) return st;
+  if (image->ndim != 2) return TC_ESHAPE;
+  if (image->dtype != TC_U8 && image->dtype != TC_F16 && image->dtype != TC_F32) return TC_EDTYPE;
+  if (stencil < TC_STENCIL_FD2 || stencil > TC_STENCIL_SOBEL3) return TC_EINVAL;
+  const int k = stencil >= TC_STENCIL_PREWITT3 ? 3 : 2;
+  const int64_t H = image->shape[0], W = image->shape[1];
+  if (H > (1LL << 24) || W > (1LL << 24)) return TC_ESHAPE;
+  const int64_t Ho = H >= k ? H - k + 1 : 0, Wo = W >= k ? W - k + 1 : 0;
+  const tc_tensor* outs[4] = {ex, ey, mag, dir};
+  float* ptr[4];
+  int64_t s0[4], s1[4];
+  for (int q = 0; q < 4; ++q) {
+    const tc_tensor* t = outs[q];
+    ptr[q] = nullptr;
+    s0[q] = s1[q] = 0;
+    if (!t || !t->data) continue;
+    if ((st = check_tensor(t, true)) != TC_OK) return st;
+    if (t->ndim != 2) return TC_ESHAPE;
+    if (t->dtype != TC_F32) return TC_EDTYPE;
+    if (t->shape[0] != Ho || t->shape[1] != Wo) return TC_ESHAPE;
+    ptr[q] = reinterpret_cast<float*>(t->data);
+    s0[q] = t->stride[0];
+    s1[q] = t->stride[1];
+  }
+  const GradOut o{ptr[0], s0[0], s1[0], ptr[1], s0[1], s1[1], ptr[2], s0[2], s1[2], ptr[3], s0[3], s1[3]};
+  if (!o.ex && !o.ey && !o.mag && !o.dir) return TC_OK;
+  const Image2D src{image->data, image->dtype, image->stride[0], image->stride[1]};
+  return hip_status(launch_gradient(src, stencil, (int)Ho, (int)Wo, o, reinterpret_cast<hipStream_t>(stream)));
+}
+
+extern "C" int tc_ttc_reselect(const tc_ttc_level* levels, int64_t n_pairs, int32_t levels_per_pair, int32_t rule,
+                               tc_ttc_pick* picks_out, void* stream) {
+  if (n_pairs < 0 || levels_per_pair < 1 || levels_per_pair > 16) return TC_EINVAL;
+  if (rule != TC_SELECT_DECREASING_TTC && rule != TC_SELECT_MIN_RESIDUAL) return TC_EINVAL;
+  if (n_pairs > (1LL << 40)) return TC_EINVAL;
+  if (n_pairs == 0) return TC_OK;
+  if (!levels || !picks_out) return TC_EINVAL;
+  return hip_status(launch_ttc_reselect(levels, n_pairs, levels_per_pair, rule, picks_out,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
 // ============================================================================ time to contact
 struct tc_ttc_plan {
   int dtype = 0;

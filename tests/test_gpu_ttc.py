@@ -198,3 +198,65 @@ def test_plan_reset_matches_fresh_plan(api):
     torch.cuda.synchronize()
     assert [x.tobytes() for x in plan.results()] == ra
     plan.close()
+
+
+def _resid_tol(r, a):
+    """The residual bound of check_pair, per cube."""
+    return (1e-3 * abs(r["resid"]) + 1e-6 * a[9]) / r["n"]
+
+
+@pytest.mark.parametrize("dtype,case", [("u8", 31), ("f16", 32)])
+def test_reselect_rules(api, dtype, case):
+    """tc_ttc_reselect on a plan's device records: the decreasing-TTC rule
+    reproduces the plan's own picks bitwise; the residual rule equals the
+    oracle's rule applied to the same device records (exact decisions on the
+    same numbers), and the oracle's rule on its own records wherever no two
+    valid levels are within tolerance of a tie."""
+    levels = 4
+    specs, vids = _small_batch(dtype, case)
+    plan = api.TTCPlan([api.seq_from_frames(v, levels) for v in vids], vids[0].dtype, keep=vids)
+    plan.run()
+    n = plan.n_pairs
+    p0 = api.ttc_reselect(plan.levels_buf, n, levels, "decreasing_ttc")
+    p1 = api.ttc_reselect(plan.levels_buf, n, levels, "min_residual")
+    torch.cuda.synchronize()
+    recs, picks = plan.results()
+    assert api.decode_picks(p0[: n * 56]).tobytes() == picks.tobytes()
+    got = api.decode_picks(p1[: n * 56])
+    q = 0
+    differs = 0
+    for s, v in zip(specs, vids):
+        fr = _frames_np(v)
+        for t in range(fr.shape[0] - 1):
+            rec = recs[q * levels:(q + 1) * levels]
+            dev = [{k: rec[l][k] for k in ("ttc", "status", "resid", "n")} for l in range(levels)]
+            l1 = O.select_level_residual(dev)
+            assert got[q]["level"] == l1
+            for k in ("ttc", "x0", "y0", "A", "B", "C", "status"):
+                assert got[q][k].tobytes() == rec[l1][k].tobytes(), (q, k)
+            differs += int(l1 != picks[q]["level"])
+            ref = O.ttc_pair(fr[t], fr[t + 1], levels)
+            pa, pb = O.pyramid(fr[t], levels), O.pyramid(fr[t + 1], levels)
+            valid = [l for l in range(levels) if ref[l]["status"] == 0 and ref[l]["ttc"] > 0]
+            per = {l: (ref[l]["resid"] / ref[l]["n"], _resid_tol(ref[l], abs_sums(pa[l], pb[l], l, *fr[t].shape)))
+                   for l in valid}
+            tie = any(abs(per[i][0] - per[j][0]) <= per[i][1] + per[j][1] for i in valid for j in valid if i < j)
+            if not tie:
+                assert l1 == O.select_level_residual(ref), (q, per)
+            q += 1
+    assert q == n
+    print(f"[reselect {dtype}] {n} pairs, the residual rule picks another level on {differs}")
+
+
+def test_reselect_rejections(api):
+    from paper_1612_08825_amd import _lib as L
+
+    lib = api._lib()
+    buf = torch.zeros(4 * 152, dtype=torch.uint8, device="cuda")
+    out = torch.zeros(56, dtype=torch.uint8, device="cuda")
+    ptr = buf.data_ptr()
+    assert lib.tc_ttc_reselect(ptr, 1, 4, 2, out.data_ptr(), None) == L.TC_EINVAL
+    assert lib.tc_ttc_reselect(ptr, 1, 0, 0, out.data_ptr(), None) == L.TC_EINVAL
+    assert lib.tc_ttc_reselect(ptr, -1, 4, 0, out.data_ptr(), None) == L.TC_EINVAL
+    assert lib.tc_ttc_reselect(None, 1, 4, 0, out.data_ptr(), None) == L.TC_EINVAL
+    assert lib.tc_ttc_reselect(None, 0, 4, 0, None, None) == L.TC_OK
