@@ -20,6 +20,9 @@ Modules:
               FOE / TTC, multi-scale level selection (Time to Contact)
   gradient -- image gradient with the 2x2 / 3x3 masks, its magnitude and
               direction (Discrete Derivatives; Convolutions)
+  variant  -- time to contact with the centred 3x3 Prewitt / Sobel stencils
+              and the pyramid low-pass filter (Convolutions; Time to Contact,
+              Results)
 """
 from .conv import conv, conv_full, conv_at, conv_bruteforce, conv_out_shape  # noqa: F401
 from .pyramid import pyramid, reduce2  # noqa: F401
@@ -42,3 +45,4 @@ from .ttc import (  # noqa: F401
     ttc_sequence,
 )
 from .gradient import STENCILS, apply_mask, gradient, masks  # noqa: F401
+from . import variant  # noqa: F401,E402
