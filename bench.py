@@ -57,7 +57,7 @@ def parse():
 # ----------------------------------------------------------------------------- measured traffic
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttc_fused_batched64_f16_L4.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_08825_amd", "csrc", f)
-                  for f in ("ttc.hip", "device_common.hpp", "internal.hpp")]
+                  for f in ("ttc.hip", "device_common.hpp", "internal.hpp", "solve.hpp")]
 
 
 def profiled_traffic():
@@ -341,6 +341,59 @@ def multiscale_mse(api, torch, np):
     return res
 
 
+def variant_ablation(api, torch, np):
+    """Every pair of the 300-frame approaching-plane video through the
+    decomposed path with each derivative stencil (2x2x2 cube, centred Prewitt
+    3x3, centred Sobel 3x3) and pyramid (block mean alone, or followed by the
+    binomial low-pass): TTC / FOE mean squared error against the analytic
+    ground truth per static level and for the multi-scale choice, and the
+    path's throughput (one call per pair, buffers allocated once)."""
+    from paper_1612_08825_amd import synth
+
+    v = synth.multiscale_video(device="cuda")
+    gt = v.ttc_gt()
+    foe = np.array(v.foe)
+    F, H, W = v.frames.shape
+    n = F - 1
+    out = {}
+    for stencil in ("cube", "prewitt3", "sobel3"):
+        for lowpass in ("none", "binomial3"):
+            ws = torch.empty(api.ttc_variant_workspace_size(H, W, LEVELS, stencil, lowpass), dtype=torch.uint8,
+                             device="cuda")
+            lv = torch.empty(n * LEVELS * 152, dtype=torch.uint8, device="cuda")
+            pk = torch.empty(n * 56, dtype=torch.uint8, device="cuda")
+
+            def one_pass():
+                for t in range(n):
+                    api.ttc_solve_variant(v.frames[t], v.frames[t + 1], LEVELS, stencil, lowpass, ws=ws,
+                                          out=(lv[t * LEVELS * 152:(t + 1) * LEVELS * 152], pk[t * 56:(t + 1) * 56]))
+
+            one_pass()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            one_pass()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            recs, picks = api.decode_levels(lv), api.decode_picks(pk)
+            row = {"ms_per_pair": round(ms / n, 4), "Gpixel_per_s": round(n * H * W / (ms * 1e-3) / 1e9, 3)}
+            for l in range(LEVELS):
+                r = recs[l::LEVELS]
+                ok = r["status"] == 0
+                row[f"level{l}"] = {"ttc_mse": float(np.mean((r["ttc"][ok] - gt[ok]) ** 2)),
+                                    "foe_mse_px2": float(np.mean((r["x0"][ok] - foe[0]) ** 2
+                                                                 + (r["y0"][ok] - foe[1]) ** 2)),
+                                    "ok_pairs": int(ok.sum())}
+            ok = picks["status"] == 0
+            row["multiscale"] = {"ttc_mse": float(np.mean((picks["ttc"][ok] - gt[ok]) ** 2)),
+                                 "foe_mse_px2": float(np.mean((picks["x0"][ok] - foe[0]) ** 2
+                                                              + (picks["y0"][ok] - foe[1]) ** 2)),
+                                 "ok_pairs": int(ok.sum()),
+                                 "level_histogram": np.bincount(picks["level"][ok], minlength=LEVELS).tolist()}
+            out[f"{stencil}+{lowpass}"] = row
+            del ws, lv, pk
+    return out
+
+
 # ----------------------------------------------------------------------------- plain path
 def plain_path(api, torch, vids, reps=3):
     """The same pairs, one tc_ttc_solve call (fused + finishing launch) per pair,
@@ -599,6 +652,7 @@ def main():
     if not args.profile:
         vs_oracle = gpu_vs_oracle(api, torch, np, oracle_pairs)
         ms_mse = multiscale_mse(api, torch, np)
+        ms_mse["variants"] = variant_ablation(api, torch, np)
         print("[bench] accuracy done", file=sys.stderr, flush=True)
 
     plain = None

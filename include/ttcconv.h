@@ -333,6 +333,39 @@ int tc_ttc_reselect(const tc_ttc_level* levels, int64_t n_pairs, int32_t levels_
 int tc_ttc_solve_batched(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, void* ws, size_t ws_bytes,
                          tc_ttc_level* levels_out, tc_ttc_pick* picks_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Time to contact with another derivative stencil or a pyramid low-pass
+ *
+ * Convolutions section: the centred 3x3 Prewitt and Sobel masks as the
+ * derivative stencil; Time to Contact, Results: a low-pass filter after each
+ * block mean.  The same least-squares estimate and multi-scale rule as
+ * tc_ttc_solve, through materialised levels (a comparison path: each level
+ * image is written once and read back).
+ *
+ * stencil: TC_STENCIL_FD2 (the 2x2x2 cube of tc_ttc_solve, estimates between
+ *   pixels, (H_l-1)(W_l-1) of them), TC_STENCIL_PREWITT3 or TC_STENCIL_SOBEL3:
+ *   E_x = (M_x * P0 + M_x * P1) / 2 with M_x the smoothing [1,1,1]/3 or
+ *   [1,2,1]/4 across x times the centred difference [-1,0,1]/2 along x (E_y
+ *   transposed), E_t = the 2-D smoothing s s^T applied to P1 - P0, at every
+ *   pixel with a full 3x3 neighbourhood ((H_l-2)(W_l-2) estimates), centred at
+ *   x = 2^l (j + 1/2) - W/2.  TC_STENCIL_ROBERTS is rejected (TC_EINVAL).
+ * lowpass: TC_LOWPASS_NONE, or TC_LOWPASS_BINOMIAL3: after each 2x2 block mean
+ *   the level is filtered by [1,2,1]/4 along rows and columns with clamped
+ *   borders (level 0 is not filtered; level sizes are unchanged).
+ * prev, next: 2-D U8, F16 or F32 frames of one shape (strided); every level
+ * must hold at least 2x2 (cube) or 3x3 pixels (TC_ESHAPE otherwise).  ws: device
+ * workspace of tc_ttc_variant_workspace_size bytes (TC_ENOMEM if smaller).
+ * levels_out[levels], pick_out[1]: device memory.  Derivatives are FP32, G,
+ * products and sums FP64 (deterministic order).  Launches only.
+ * ------------------------------------------------------------------------ */
+#define TC_LOWPASS_NONE 0
+#define TC_LOWPASS_BINOMIAL3 1
+int tc_ttc_variant_workspace_size(int64_t H, int64_t W, int32_t levels, int32_t stencil, int32_t lowpass,
+                                  size_t* ws_bytes);
+int tc_ttc_solve_variant(const tc_tensor* prev, const tc_tensor* next, int32_t levels, int32_t stencil,
+                         int32_t lowpass, void* ws, size_t ws_bytes, tc_ttc_level* levels_out, tc_ttc_pick* pick_out,
+                         void* stream);
+
 /* Workspace bytes for tc_ttc_solve on an H x W pair with `levels` levels. */
 int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_t* ws_bytes);
 /* One frame pair (2-D U8 or F16 tensors of equal shape): levels_out[levels]

@@ -25,6 +25,7 @@ MODES = {"full": TC_FULL, "same": TC_SAME, "valid": TC_VALID}
 TC_PHASE_FUSED, TC_PHASE_FINISH = 1, 2
 TC_STENCIL_FD2, TC_STENCIL_ROBERTS, TC_STENCIL_PREWITT3, TC_STENCIL_SOBEL3 = 0, 1, 2, 3
 TC_SELECT_DECREASING_TTC, TC_SELECT_MIN_RESIDUAL = 0, 1
+TC_LOWPASS_NONE, TC_LOWPASS_BINOMIAL3 = 0, 1
 
 
 class TcTensor(C.Structure):
@@ -97,6 +98,8 @@ SIGNATURES = {
     "tc_ttc_plan_destroy": (None, [_P]),
     "tc_ttc_solve_batched": (_I, [C.POINTER(TcSeq), _I32, _I32, _P, _SZ, _P, _P, _P]),
     "tc_ttc_workspace_size": (_I, [_I64, _I64, _I32, C.POINTER(_SZ)]),
+    "tc_ttc_variant_workspace_size": (_I, [_I64, _I64, _I32, _I32, _I32, C.POINTER(_SZ)]),
+    "tc_ttc_solve_variant": (_I, [_T, _T, _I32, _I32, _I32, _P, _SZ, _P, _P, _P]),
     "tc_ttc_solve": (_I, [_T, _T, _I32, _P, _SZ, _P, _P, _P]),
 }
 

@@ -228,6 +228,38 @@ def ttc_solve(prev: torch.Tensor, nxt: torch.Tensor, levels: int = 1, ws: Option
     return out
 
 
+VARIANT_STENCILS = {"cube": L.TC_STENCIL_FD2, "prewitt3": L.TC_STENCIL_PREWITT3, "sobel3": L.TC_STENCIL_SOBEL3}
+LOWPASS = {"none": L.TC_LOWPASS_NONE, "binomial3": L.TC_LOWPASS_BINOMIAL3}
+
+
+def ttc_variant_workspace_size(H: int, W: int, levels: int, stencil: str = "cube", lowpass: str = "none") -> int:
+    n = C.c_size_t(0)
+    L.check("tc_ttc_variant_workspace_size",
+            _lib().tc_ttc_variant_workspace_size(H, W, levels, VARIANT_STENCILS[stencil], LOWPASS[lowpass],
+                                                 C.byref(n)))
+    return n.value
+
+
+def ttc_solve_variant(prev: torch.Tensor, nxt: torch.Tensor, levels: int = 1, stencil: str = "cube",
+                      lowpass: str = "none", ws: Optional[torch.Tensor] = None,
+                      out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, stream=None):
+    """One frame pair with the given derivative stencil and pyramid low-pass ->
+    (levels buffer [levels*152 B], pick buffer [56 B]) on the device."""
+    H, W = prev.shape
+    nbytes = ttc_variant_workspace_size(H, W, levels, stencil, lowpass)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=prev.device)
+    if out is None:
+        out = (torch.empty(levels * L.LEVEL_DTYPE.itemsize, dtype=torch.uint8, device=prev.device),
+               torch.empty(L.PICK_DTYPE.itemsize, dtype=torch.uint8, device=prev.device))
+    L.check("tc_ttc_solve_variant",
+            _lib().tc_ttc_solve_variant(C.byref(_desc(prev)), C.byref(_desc(nxt)), levels, VARIANT_STENCILS[stencil],
+                                        LOWPASS[lowpass], C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        C.c_void_p(out[0].data_ptr()), C.c_void_p(out[1].data_ptr()),
+                                        _stream(stream)))
+    return out
+
+
 def seq_from_frames(frames: torch.Tensor, levels: int) -> L.TcSeq:
     """A [F, H, W] u8/f16 video tensor (row-contiguous) as a tc_seq descriptor."""
     if frames.dim() != 3 or frames.stride(2) != 1:

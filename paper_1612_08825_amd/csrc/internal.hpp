@@ -64,6 +64,20 @@ struct Image2D {
 hipError_t launch_gradient(const Image2D& src, int stencil, int Ho, int Wo, const GradOut& o, hipStream_t s);
 hipError_t launch_pyramid_level(const Image2D& src, float* dst, int64_t d0, int64_t d1, int Ho, int Wo,
                                 hipStream_t s);
+// ---------------------------------------------------------------- decomposed TTC (stencil / low-pass variants)
+struct VariantLevels {
+  int levels;
+  int blocks[TC_MAX_LEVELS];        // work-groups of the sums kernel per level
+  int64_t part_off[TC_MAX_LEVELS];  // first partial (in units of 10 doubles) per level
+  int64_t n[TC_MAX_LEVELS];         // positions summed per level
+};
+int variant_sum_blocks(int64_t positions);
+hipError_t launch_lowpass3(const float* src, int H, int W, float* dst, hipStream_t s);
+hipError_t launch_stencil_sums(int stencil, const Image2D& a, const Image2D& b, int Hl, int Wl, int level, int H0,
+                               int W0, double* part, int blocks, hipStream_t s);
+hipError_t launch_variant_finish(const double* part, const VariantLevels& lv, tc_ttc_level* out, tc_ttc_pick* pick,
+                                 hipStream_t s);
+
 hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, void* ex, void* ey, void* et,
                        int odt, const int64_t* os0, const int64_t* os1, hipStream_t s);
 

@@ -40,6 +40,7 @@
 
 #include "device_common.hpp"
 #include "internal.hpp"
+#include "solve.hpp"
 
 namespace ttc {
 namespace {
@@ -457,77 +458,6 @@ __device__ __forceinline__ int sum_scale_exp(int l, int q) {
   }
 }
 
-#pragma clang fp contract(off)
-__device__ void solve_level(const double* s, tc_ttc_level& r) {
-  const double nan = __builtin_nan("");
-  for (int q = 0; q < TC_NUM_SUMS; ++q) r.sums[q] = s[q];
-  r.A = r.B = r.C = r.ttc = r.x0 = r.y0 = r.resid = nan;
-  r.status = TC_OK;
-  for (int q = 0; q < TC_NUM_SUMS; ++q)
-    if (!isfinite(s[q])) {
-      r.status = TC_NONFINITE;
-      return;
-    }
-  double M[3][4] = {{s[0], s[1], s[3], -s[6]}, {s[1], s[2], s[4], -s[7]}, {s[3], s[4], s[5], -s[8]}};
-  if (M[0][0] <= 0.0 || M[1][1] <= 0.0 || M[2][2] <= 0.0) {
-    r.status = TC_SINGULAR;
-    return;
-  }
-  double dg[3];
-  for (int i = 0; i < 3; ++i) dg[i] = 1.0 / sqrt(M[i][i]);
-  double a[3][4];
-  for (int i = 0; i < 3; ++i) {
-    for (int j = 0; j < 3; ++j) a[i][j] = dg[i] * M[i][j] * dg[j];
-    a[i][3] = dg[i] * M[i][3];
-  }
-  double minpiv = 1e300;
-  for (int c = 0; c < 3; ++c) {
-    int p = c;
-    for (int i = c + 1; i < 3; ++i)
-      if (fabs(a[i][c]) > fabs(a[p][c])) p = i;
-    if (p != c)
-      for (int j = 0; j < 4; ++j) {
-        const double t = a[c][j];
-        a[c][j] = a[p][j];
-        a[p][j] = t;
-      }
-    const double piv = a[c][c];
-    minpiv = fmin(minpiv, fabs(piv));
-    if (piv == 0.0) break;
-    for (int i = c + 1; i < 3; ++i) {
-      const double f = a[i][c] / piv;
-      for (int j = c; j < 4; ++j) a[i][j] = a[i][j] - f * a[c][j];
-    }
-  }
-  if (!(minpiv >= 1e-6)) {
-    r.status = TC_SINGULAR;
-    return;
-  }
-  double v[3];
-  for (int i = 2; i >= 0; --i) {
-    double acc = a[i][3];
-    for (int j = i + 1; j < 3; ++j) acc = acc - a[i][j] * v[j];
-    v[i] = acc / a[i][i];
-  }
-  const double A = dg[0] * v[0], B = dg[1] * v[1], C = dg[2] * v[2];
-  r.A = A;
-  r.B = B;
-  r.C = C;
-  if (C == 0.0) {
-    r.ttc = copysign(__builtin_inf(), C);
-  } else {
-    r.ttc = 1.0 / C;
-    r.x0 = -A / C;
-    r.y0 = -B / C;
-  }
-  r.resid = s[9] + A * s[6] + B * s[7] + C * s[8];
-}
-#pragma clang fp contract(on)
-
-__device__ __forceinline__ double level_key(const tc_ttc_level& r) {
-  if (r.status != TC_OK || !isfinite(r.ttc) || !(r.ttc > 0.0)) return __builtin_inf();
-  return r.ttc;
-}
 
 // The multi-scale choice again, from level records already in device memory:
 // rule 0 descends while the TTC keeps decreasing (as ttc_finish does), rule 1

@@ -1,0 +1,224 @@
+// Time to contact of one frame pair through materialised levels, with a choice
+// of derivative stencil and of the pyramid low-pass filter (the decomposed
+// path used to compare the paper's variants; the fused pass serves the
+// 2x2x2 cube without a low-pass filter).
+//
+// lowpass3:      P <- [1, 2, 1]/4 along rows and columns, borders clamped
+//                (Time to Contact, Results: a low-pass filter after the block
+//                mean; the filter itself is a reading, binomial).
+// stencil_sums:  one level's ten sums of the normal equations.  Per position
+//                the derivatives are formed in FP32 from the two frames, then
+//                G, the products and every sum are FP64; each block writes its
+//                partial sums (fixed order, deterministic).
+//   ST 0 cube      the 2x2x2 first-difference cube between pixels (i, j) and
+//                  (i+1, j+1), centred at x = 2^l (j + 1) - W0/2
+//   ST 2 prewitt3  E_x = (M_x * P0 + M_x * P1)/2, M_x = [1,1,1]^T/3 (x) [-1,0,1]/2,
+//   ST 3 sobel3    M_x = [1,2,1]^T/4 (x) [-1,0,1]/2; E_y with the transposes;
+//                  E_t = (s s^T) * (P1 - P0); centred at pixel (i, j),
+//                  x = 2^l (j + 1/2) - W0/2, 1 <= i <= H_l - 2, 1 <= j <= W_l - 2
+//                (Convolutions section: the centred 3x3 masks)
+//   Spatial derivatives are per base pixel (divided by 2^l).
+// variant_finish: per level the block partials in a fixed order (FP64), the
+//                3x3 solve, and the multi-scale choice by the decreasing-TTC rule.
+#include <math.h>
+
+#include "device_common.hpp"
+#include "internal.hpp"
+#include "solve.hpp"
+
+namespace ttc {
+namespace {
+
+constexpr int kSumThreads = 256;
+
+__global__ __launch_bounds__(256) void lowpass3(const float* __restrict__ src, int H, int W,
+                                                 float* __restrict__ dst) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= W) return;
+  const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < W ? j + 1 : W - 1;
+  float acc = 0.f;
+  const float wr[3] = {0.25f, 0.5f, 0.25f};
+#pragma unroll
+  for (int a = -1; a <= 1; ++a) {
+    const int r = min(max(i + a, 0), H - 1);
+    const float* row = src + (int64_t)r * W;
+    const float h = 0.25f * row[jm] + 0.5f * row[j] + 0.25f * row[jp];
+    acc += wr[a + 1] * h;
+  }
+  dst[(int64_t)i * W + j] = acc;
+}
+
+struct Plane {
+  const void* p;
+  int64_t s0, s1;
+};
+
+template <typename T>
+__device__ __forceinline__ float px(const Plane& q, int r, int c) {
+  return to_f32<T>(static_cast<const T*>(q.p)[(int64_t)r * q.s0 + (int64_t)c * q.s1]);
+}
+
+// Sum of doubles over the 64 lanes of a wave (butterfly, every lane gets it).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+template <typename T, int ST>
+__global__ __launch_bounds__(kSumThreads) void stencil_sums(Plane a, Plane b, int Hl, int Wl, int level, int H0,
+                                                             int W0, double* __restrict__ part) {
+  constexpr int K = ST == 0 ? 2 : 3;
+  constexpr int B0 = ST == 0 ? 0 : 1;  // first position row / column
+  const int nr = Hl - K + 1, nc = Wl - K + 1;
+  const int64_t n = (int64_t)nr * nc;
+  const double sl = ldexp(1.0, level);
+  const double cx = ST == 0 ? 1.0 : 0.5;  // position of pixel j's estimate: 2^l (j + cx) - W0/2
+  double acc[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * kSumThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kSumThreads) {
+    const int i = B0 + (int)(p / nc), j = B0 + (int)(p % nc);
+    float fx, fy, ft;
+    if constexpr (ST == 0) {
+      const float a00 = px<T>(a, i, j), a01 = px<T>(a, i, j + 1), a10 = px<T>(a, i + 1, j), a11 = px<T>(a, i + 1, j + 1);
+      const float b00 = px<T>(b, i, j), b01 = px<T>(b, i, j + 1), b10 = px<T>(b, i + 1, j), b11 = px<T>(b, i + 1, j + 1);
+      const float s00 = a00 + b00, s01 = a01 + b01, s10 = a10 + b10, s11 = a11 + b11;
+      fx = ((s01 - s00) + (s11 - s10)) * 0.25f;
+      fy = ((s10 + s11) - (s00 + s01)) * 0.25f;
+      ft = ((b00 - a00) + (b01 - a01) + ((b10 - a10) + (b11 - a11))) * 0.25f;
+    } else {
+      constexpr float w1 = ST == 2 ? 1.f : 2.f;        // centre weight of the smoothing
+      constexpr float sd = ST == 2 ? 1.f / 12.f : 1.f / 16.f;  // (1/2 frames)(1/2 difference)(1/sum w)
+      constexpr float st = ST == 2 ? 1.f / 9.f : 1.f / 16.f;   // 1/(sum w)^2
+      float S[3][3], D[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float u = px<T>(a, i - 1 + r, j - 1 + c), v = px<T>(b, i - 1 + r, j - 1 + c);
+          S[r][c] = u + v;
+          D[r][c] = v - u;
+        }
+      fx = ((S[0][2] - S[0][0]) + w1 * (S[1][2] - S[1][0]) + (S[2][2] - S[2][0])) * sd;
+      fy = ((S[2][0] - S[0][0]) + w1 * (S[2][1] - S[0][1]) + (S[2][2] - S[0][2])) * sd;
+      const float r0 = D[0][0] + w1 * D[0][1] + D[0][2];
+      const float r1 = D[1][0] + w1 * D[1][1] + D[1][2];
+      const float r2 = D[2][0] + w1 * D[2][1] + D[2][2];
+      ft = (r0 + w1 * r1 + r2) * st;
+    }
+    const double ex = (double)fx / sl, ey = (double)fy / sl, et = (double)ft;
+    const double x = sl * (j + cx) - 0.5 * W0, y = sl * (i + cx) - 0.5 * H0;
+    const double g = x * ex + y * ey;
+    acc[0] += ex * ex;
+    acc[1] += ex * ey;
+    acc[2] += ey * ey;
+    acc[3] += g * ex;
+    acc[4] += g * ey;
+    acc[5] += g * g;
+    acc[6] += ex * et;
+    acc[7] += ey * et;
+    acc[8] += g * et;
+    acc[9] += et * et;
+  }
+  __shared__ double red[kSumThreads / 64][10];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const double v = wave_sum(acc[q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSumThreads / 64; ++w) s += red[w][threadIdx.x];
+    part[(int64_t)blockIdx.x * 10 + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(64) void variant_finish(const double* __restrict__ part, VariantLevels lv,
+                                                     tc_ttc_level* __restrict__ out, tc_ttc_pick* __restrict__ pick) {
+  __shared__ tc_ttc_level res[TC_MAX_LEVELS];
+  const int l = threadIdx.x;
+  if (l < lv.levels) {
+    double s[10];
+    for (int q = 0; q < 10; ++q) s[q] = 0.0;
+    const double* p = part + lv.part_off[l] * 10;
+    for (int bk = 0; bk < lv.blocks[l]; ++bk)
+      for (int q = 0; q < 10; ++q) s[q] += p[(int64_t)bk * 10 + q];
+    tc_ttc_level r;
+    solve_level(s, r);
+    r.n = lv.n[l];
+    r.level = l;
+    res[l] = r;
+    out[l] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int k = 0;
+    while (k + 1 < lv.levels && level_key(res[k + 1]) < level_key(res[k])) ++k;
+    tc_ttc_pick pk;
+    pk.ttc = res[k].ttc;
+    pk.x0 = res[k].x0;
+    pk.y0 = res[k].y0;
+    pk.A = res[k].A;
+    pk.B = res[k].B;
+    pk.C = res[k].C;
+    pk.level = k;
+    pk.status = res[k].status;
+    *pick = pk;
+  }
+}
+
+template <typename T>
+hipError_t sums_t(int stencil, const Image2D& a, const Image2D& b, int Hl, int Wl, int level, int H0, int W0,
+                  double* part, int blocks, hipStream_t s) {
+  const Plane pa{a.p, a.s0, a.s1}, pb{b.p, b.s0, b.s1};
+  const dim3 grid((unsigned)blocks), block(kSumThreads);
+  switch (stencil) {
+    case TC_STENCIL_FD2:
+      hipLaunchKernelGGL((stencil_sums<T, 0>), grid, block, 0, s, pa, pb, Hl, Wl, level, H0, W0, part);
+      break;
+    case TC_STENCIL_PREWITT3:
+      hipLaunchKernelGGL((stencil_sums<T, 2>), grid, block, 0, s, pa, pb, Hl, Wl, level, H0, W0, part);
+      break;
+    case TC_STENCIL_SOBEL3:
+      hipLaunchKernelGGL((stencil_sums<T, 3>), grid, block, 0, s, pa, pb, Hl, Wl, level, H0, W0, part);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int variant_sum_blocks(int64_t positions) {
+  const int64_t b = (positions + 4 * kSumThreads - 1) / (4 * kSumThreads);
+  return (int)(b < 1 ? 1 : b > 1024 ? 1024 : b);
+}
+
+hipError_t launch_lowpass3(const float* src, int H, int W, float* dst, hipStream_t s) {
+  if (H <= 0 || W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lowpass3, dim3((unsigned)((W + 255) / 256), (unsigned)H), dim3(256), 0, s, src, H, W, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_sums(int stencil, const Image2D& a, const Image2D& b, int Hl, int Wl, int level, int H0,
+                               int W0, double* part, int blocks, hipStream_t s) {
+  switch (a.dt) {
+    case TC_U8: return sums_t<uint8_t>(stencil, a, b, Hl, Wl, level, H0, W0, part, blocks, s);
+    case TC_F16: return sums_t<_Float16>(stencil, a, b, Hl, Wl, level, H0, W0, part, blocks, s);
+    case TC_F32: return sums_t<float>(stencil, a, b, Hl, Wl, level, H0, W0, part, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_variant_finish(const double* part, const VariantLevels& lv, tc_ttc_level* out, tc_ttc_pick* pick,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(variant_finish, dim3(1), dim3(64), 0, s, part, lv, out, pick);
+  return hipGetLastError();
+}
+
+}  // namespace ttc

@@ -714,6 +714,103 @@ extern "C" int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_
   return TC_OK;
 }
 
+namespace {
+
+// Workspace of the decomposed path: level images 1..levels-1 of both frames
+// (FP32, contiguous), one block-mean image for the low-pass filter to read,
+// and the per-block partial sums of every level.
+struct VariantLayout {
+  int64_t Hl[TC_MAX_LEVELS], Wl[TC_MAX_LEVELS];
+  size_t level_off[2][TC_MAX_LEVELS];
+  size_t tmp_off = 0, part_off = 0, total = 0;
+  VariantLevels lv{};
+};
+
+int variant_layout(int64_t H, int64_t W, int32_t levels, int32_t stencil, int32_t lowpass, VariantLayout& L) {
+  if (levels < 1 || levels > TC_MAX_LEVELS) return TC_EINVAL;
+  if (stencil != TC_STENCIL_FD2 && stencil != TC_STENCIL_PREWITT3 && stencil != TC_STENCIL_SOBEL3) return TC_EINVAL;
+  if (lowpass != TC_LOWPASS_NONE && lowpass != TC_LOWPASS_BINOMIAL3) return TC_EINVAL;
+  if (H < 1 || W < 1 || H > (1 << 20) || W > (1 << 20)) return TC_ESHAPE;
+  const int k = stencil == TC_STENCIL_FD2 ? 2 : 3;
+  int64_t parts = 0;
+  L.lv.levels = levels;
+  for (int l = 0; l < levels; ++l) {
+    L.Hl[l] = H >> l;
+    L.Wl[l] = W >> l;
+    if (L.Hl[l] < k || L.Wl[l] < k) return TC_ESHAPE;
+    const int64_t n = (L.Hl[l] - k + 1) * (L.Wl[l] - k + 1);
+    L.lv.n[l] = n;
+    L.lv.blocks[l] = variant_sum_blocks(n);
+    L.lv.part_off[l] = parts;
+    parts += L.lv.blocks[l];
+  }
+  size_t off = 0;
+  for (int f = 0; f < 2; ++f)
+    for (int l = 1; l < levels; ++l) {
+      L.level_off[f][l] = off;
+      off += align_up((size_t)(L.Hl[l] * L.Wl[l]) * sizeof(float));
+    }
+  L.tmp_off = off;
+  if (lowpass == TC_LOWPASS_BINOMIAL3 && levels > 1) off += align_up((size_t)(L.Hl[1] * L.Wl[1]) * sizeof(float));
+  L.part_off = off;
+  off += align_up((size_t)parts * 10 * sizeof(double));
+  L.total = off;
+  return TC_OK;
+}
+
+}  // namespace
+
+extern "C" int tc_ttc_variant_workspace_size(int64_t H, int64_t W, int32_t levels, int32_t stencil, int32_t lowpass,
+                                             size_t* ws_bytes) {
+  if (!ws_bytes) return TC_EINVAL;
+  VariantLayout L;
+  const int st = variant_layout(H, W, levels, stencil, lowpass, L);
+  if (st != TC_OK) return st;
+  *ws_bytes = L.total;
+  return TC_OK;
+}
+
+extern "C" int tc_ttc_solve_variant(const tc_tensor* prev, const tc_tensor* next, int32_t levels, int32_t stencil,
+                                    int32_t lowpass, void* ws, size_t ws_bytes, tc_ttc_level* levels_out,
+                                    tc_ttc_pick* pick_out, void* stream) {
+  int st;
+  if (!ws || !levels_out || !pick_out) return TC_EINVAL;
+  if ((st = check_tensor(prev, true)) != TC_OK) return st;
+  if ((st = check_tensor(next, true)) != TC_OK) return st;
+  if (prev->ndim != 2 || next->ndim != 2) return TC_ESHAPE;
+  if (prev->dtype != next->dtype) return TC_EDTYPE;
+  if (prev->dtype != TC_U8 && prev->dtype != TC_F16 && prev->dtype != TC_F32) return TC_EDTYPE;
+  if (prev->shape[0] != next->shape[0] || prev->shape[1] != next->shape[1]) return TC_ESHAPE;
+  const int64_t H = prev->shape[0], W = prev->shape[1];
+  VariantLayout L;
+  if ((st = variant_layout(H, W, levels, stencil, lowpass, L)) != TC_OK) return st;
+  if (ws_bytes < L.total) return TC_ENOMEM;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  double* part = reinterpret_cast<double*>(w + L.part_off);
+  Image2D cur[2] = {Image2D{prev->data, prev->dtype, prev->stride[0], prev->stride[1]},
+                    Image2D{next->data, next->dtype, next->stride[0], next->stride[1]}};
+  for (int l = 0; l < levels; ++l) {
+    const int Hl = (int)L.Hl[l], Wl = (int)L.Wl[l];
+    if (l > 0)
+      for (int f = 0; f < 2; ++f) {
+        float* dst = reinterpret_cast<float*>(w + L.level_off[f][l]);
+        if (lowpass == TC_LOWPASS_BINOMIAL3) {
+          float* tmp = reinterpret_cast<float*>(w + L.tmp_off);
+          if (launch_pyramid_level(cur[f], tmp, Wl, 1, Hl, Wl, s) != hipSuccess) return TC_EDEVICE;
+          if (launch_lowpass3(tmp, Hl, Wl, dst, s) != hipSuccess) return TC_EDEVICE;
+        } else if (launch_pyramid_level(cur[f], dst, Wl, 1, Hl, Wl, s) != hipSuccess) {
+          return TC_EDEVICE;
+        }
+        cur[f] = Image2D{dst, TC_F32, Wl, 1};
+      }
+    if (launch_stencil_sums(stencil, cur[0], cur[1], Hl, Wl, l, (int)H, (int)W, part + L.lv.part_off[l] * 10,
+                            L.lv.blocks[l], s) != hipSuccess)
+      return TC_EDEVICE;
+  }
+  return hip_status(launch_variant_finish(part, L.lv, levels_out, pick_out, s));
+}
+
 extern "C" int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_t levels, void* ws, size_t ws_bytes,
                             tc_ttc_level* levels_out, tc_ttc_pick* pick_out, void* stream) {
   if (!ws || !levels_out || !pick_out) return TC_EINVAL;

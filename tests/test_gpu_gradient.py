@@ -74,7 +74,9 @@ def check(api, img_np, stencil, got, ctx):
 
 @pytest.mark.parametrize("stencil", ["fd2", "roberts", "prewitt3", "sobel3"])
 @pytest.mark.parametrize("dtype", ["u8", "f16", "f32"])
-@pytest.mark.parametrize("H,W", [(37, 300), (64, 257), (5, 1031), (3, 3)])
+# W a multiple of 4 takes the vector kernel (aligned input rows; output rows of
+# any alignment), other widths the any-stride kernel
+@pytest.mark.parametrize("H,W", [(37, 300), (64, 257), (5, 1031), (3, 3), (45, 1028), (9, 8), (2, 4), (70, 2052)])
 def test_gradient_matches_oracle(api, stencil, dtype, H, W):
     img = image(H, W, dtype, seed=H * 1000 + W)
     got = api.gradient(torch.from_numpy(img).cuda(), stencil)
@@ -136,3 +138,32 @@ def test_rejections(api):
     assert lib.tc_gradient(d, 0, C.byref(api._desc(bad_dtype)), None, None, None, None) == L.TC_EDTYPE
     i32 = torch.zeros((8, 8), dtype=torch.int32, device="cuda")
     assert lib.tc_gradient(C.byref(api._desc(i32)), 0, None, None, None, None, None) == L.TC_EDTYPE
+
+
+@pytest.mark.parametrize("stencil", ["fd2", "sobel3"])
+@pytest.mark.parametrize("dtype", ["u8", "f16", "f32"])
+def test_vector_kernel_equals_any_stride_kernel(api, stencil, dtype):
+    """The same image through both kernels (an odd row stride forces the
+    any-stride one): equal results; outputs whose rows start at every 4-byte
+    offset of a 16-byte line."""
+    H, W = 23, 1540
+    img = image(H, W, dtype, seed=77)
+    k = 3 if stencil == "sobel3" else 2
+    Ho, Wo = H - k + 1, W - k + 1
+    dense = torch.from_numpy(img).cuda()
+    odd = torch.empty((H, W + 1), dtype=dense.dtype, device="cuda")[:, :W]
+    odd.copy_(dense)
+    assert odd.stride(0) % 4 != 0
+    names = ("ex", "ey", "mag", "dir")
+    a = api.gradient(dense, stencil)
+    b = api.gradient(odd, stencil)
+    # outputs offset by 1..3 floats inside rows of stride Wo + 5
+    par = {n: torch.full((Ho, Wo + 5), -9.0, device="cuda") for n in names}
+    c = api.gradient(dense, stencil, out={n: par[n][:, 1 + i % 3:1 + i % 3 + Wo] for i, n in enumerate(names)})
+    torch.cuda.synchronize()
+    for i, n in enumerate(names):
+        assert torch.equal(a[n], b[n]), n
+        assert torch.equal(a[n], c[n]), n
+        off = 1 + i % 3
+        assert bool((par[n][:, :off] == -9).all()) and bool((par[n][:, off + Wo:] == -9).all()), n
+    check(api, img, stencil, a, ("vec", stencil, dtype))
