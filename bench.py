@@ -232,6 +232,47 @@ def conv_sweep(api, torch, steps, use_graph=True):
     return out
 
 
+def fft_crossover(api, torch, steps):
+    """Direct convolution against the FFT branch on a 2048 x 2048 FP32 image,
+    full mode, square N(0,1) kernels of growing size: graph-replayed time per
+    launch of each, and the smallest kernel size at which the FFT branch wins
+    (the paper's hybrid threshold, re-measured)."""
+    import numpy as np
+
+    n = 2048
+    rng = np.random.default_rng(13)
+    x = torch.from_numpy(rng.uniform(0, 1, (n, n)).astype(np.float32)).cuda()
+    rows = []
+    for K in (7, 15, 23, 31, 39, 47, 63):
+        k = torch.from_numpy(rng.normal(0, 1, (K, K)).astype(np.float32)).cuda()
+        y = torch.empty((n + K - 1, n + K - 1), device="cuda")
+        ws = torch.empty(api.conv2d_fft_workspace_size(x, k, "full"), dtype=torch.uint8, device="cuda")
+        res = {"K": K}
+        for name, fn in (("direct_ms", lambda: api.conv_nd(x, k, "full", out=y)),
+                         ("fft_ms", lambda: api.conv2d_fft(x, k, "full", out=y, ws=ws))):
+            fn()
+            torch.cuda.synchronize()
+            reps = max(steps, 10)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                for _ in range(reps):
+                    fn()
+            g.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            res[name] = round(e0.elapsed_time(e1) / reps, 4)
+            del g
+        rows.append(res)
+        del k, y, ws
+        torch.cuda.empty_cache()
+    wins = [r["K"] for r in rows if r["fft_ms"] < r["direct_ms"]]
+    return {"image": f"{n}x{n} f32, full mode", "cases": rows, "fft_wins_from_K": min(wins) if wins else None}
+
+
 def gradient_sweep(api, torch, steps):
     """tc_gradient on 4096 x 4096 images (every output: E_x, E_y, magnitude,
     direction), buffers rotated over >= 1 GiB, timed as a replayed graph."""
@@ -543,6 +584,7 @@ def main():
     if args.conv_only:
         conv = conv_sweep(api, torch, max(10, args.steps), use_graph=not args.profile)
         grad = gradient_sweep(api, torch, max(10, args.steps))
+        conv["fft_crossover"] = fft_crossover(api, torch, max(10, args.steps))
         print(json.dumps({"conv_sweep": conv, "gradient_sweep": grad, "device": {"cus": n_cu}}), flush=True)
         return
     if args.load_frames:
@@ -676,6 +718,8 @@ def main():
         print("[bench] conv sweep done", file=sys.stderr, flush=True)
         grad = gradient_sweep(api, torch, max(10, args.steps))
         print("[bench] gradient sweep done", file=sys.stderr, flush=True)
+        conv["fft_crossover"] = fft_crossover(api, torch, max(10, args.steps))
+        print("[bench] fft crossover done", file=sys.stderr, flush=True)
 
     serve = None
     if not args.no_serve and not args.profile:

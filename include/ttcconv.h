@@ -126,6 +126,26 @@ int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, const tc_tensor
                          const tc_tensor* y, void* stream);
 
 /* ------------------------------------------------------------------------
+ * FFT branch of 2-D convolution
+ *
+ * Convolutions section: by the convolution theorem y = F^-1(F(x) F(k)), the
+ * route the paper's hybrid FastConv takes for kernels above a size threshold
+ * (Accelerating Convolutions).  The result, modes and output extents are those
+ * of tc_conv_nd for 2-D F32 x and k; x and k are zero-padded to P x Q, the
+ * powers of two >= (H+KH-1) x (W+KW-1), transformed (radix-2 Stockham, FP32,
+ * twiddles from sincospi), multiplied, transformed back and cut to the mode.
+ * P and Q are at most 4096 (TC_ESHAPE beyond).  x and y may be strided; k is
+ * contiguous device memory.  ws: device workspace of
+ * tc_conv2d_fft_workspace_size bytes (three P x Q complex planes and two
+ * twiddle tables; TC_ENOMEM if smaller).  Error: norm-wise, about
+ * log2(P Q) * 2^-24 * ||x||_2 ||k||_1 per output (not the element-wise bound of
+ * the direct path).  Launches only.
+ * ------------------------------------------------------------------------ */
+int tc_conv2d_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes);
+int tc_conv2d_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Image pyramid
  *
  * Time to Contact, Results: down-sampling by a block-averaging filter,

@@ -82,6 +82,8 @@ SIGNATURES = {
                                  C.POINTER(C.c_float)]),
     "tc_conv_nd_separable": (_I, [_T, _T, _T, _I32, _T, _P]),
     "tc_conv_nd": (_I, [_T, _T, _I32, _T, _P]),
+    "tc_conv2d_fft_workspace_size": (_I, [_T, _T, _I32, C.POINTER(_SZ)]),
+    "tc_conv2d_fft": (_I, [_T, _T, _I32, _T, _P, _SZ, _P]),
     "tc_pyramid_shape": (_I, [_I64, _I64, _I32, C.POINTER(_I64), C.POINTER(_I64)]),
     "tc_image_pyramid": (_I, [_T, _I32, _T, _P]),
     "tc_horn_derivs": (_I, [_T, _T, _T, _T, _T, _P]),

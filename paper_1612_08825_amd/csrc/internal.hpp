@@ -43,6 +43,25 @@ struct SepConv {
 bool separable_variant(int K);
 hipError_t launch_conv_separable(const SepConv& c, hipStream_t s);
 
+// FFT branch of 2-D FP32 convolution: x (H x W, strided) and k (KH x KW,
+// contiguous) zero-padded to P x Q (powers of two, <= kFftMaxN); twiddle
+// tables twP (P/2) and twQ (Q/2); A is P x Q, B and C are Q x P complex
+// scratch; the output y (OH x OW, strided) is full index n + (o0, o1).
+constexpr int kFftMaxN = 4096;
+struct FftConv {
+  const float* x;
+  int64_t xs0, xs1;
+  int H, W;
+  const float* k;
+  int KH, KW;
+  int P, Q;
+  float2 *twP, *twQ, *A, *B, *C;
+  float* y;
+  int64_t ys0, ys1;
+  int OH, OW, o0, o1;
+};
+hipError_t launch_conv2d_fft(const FftConv& f, hipStream_t s);
+
 // Zero `bytes` (a multiple of 4) of device memory with a kernel (graph-safe).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 

@@ -289,6 +289,104 @@ extern "C" int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, cons
   return hip_status(launch_conv_separable(c, s));
 }
 
+namespace {
+
+struct FftLayout {
+  int P = 0, Q = 0;
+  size_t twP = 0, twQ = 0, A = 0, B = 0, C = 0, total = 0;
+  int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
+};
+
+size_t fft_align(size_t v) { return (v + 255) / 256 * 256; }
+
+int pow2_at_least(int64_t n) {
+  int64_t p = 2;
+  while (p < n) p <<= 1;
+  return (int)p;
+}
+
+int fft_layout(const tc_tensor* x, const tc_tensor* k, int32_t mode, FftLayout& L) {
+  if (x->dtype != TC_F32 || k->dtype != TC_F32) return TC_EDTYPE;
+  if (x->ndim != 2 || k->ndim != 2) return TC_ESHAPE;
+  int st;
+  if ((st = conv_geometry(x, k, mode, L.oshape, L.off)) != TC_OK) return st;
+  const int64_t fh = x->shape[0] + k->shape[0] - 1, fw = x->shape[1] + k->shape[1] - 1;
+  if (fh > kFftMaxN || fw > kFftMaxN) return TC_ESHAPE;
+  L.P = pow2_at_least(fh);
+  L.Q = pow2_at_least(fw);
+  size_t o = 0;
+  L.twP = o;
+  o += fft_align((size_t)(L.P / 2) * sizeof(float2));
+  L.twQ = o;
+  o += fft_align((size_t)(L.Q / 2) * sizeof(float2));
+  const size_t plane = fft_align((size_t)L.P * L.Q * sizeof(float2));
+  L.A = o;
+  L.B = o + plane;
+  L.C = o + 2 * plane;
+  L.total = o + 3 * plane;
+  return TC_OK;
+}
+
+}  // namespace
+
+extern "C" int tc_conv2d_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes) {
+  if (!x || !k || !ws_bytes) return TC_EINVAL;
+  int st;
+  if ((st = check_tensor(x, false)) != TC_OK) return st;
+  if ((st = check_tensor(k, false)) != TC_OK) return st;
+  FftLayout L;
+  if ((st = fft_layout(x, k, mode, L)) != TC_OK) return st;
+  *ws_bytes = L.total;
+  return TC_OK;
+}
+
+extern "C" int tc_conv2d_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws,
+                             size_t ws_bytes, void* stream) {
+  int st;
+  if ((st = check_tensor(x, true)) != TC_OK) return st;
+  if ((st = check_tensor(k, true)) != TC_OK) return st;
+  if ((st = check_tensor(y, true)) != TC_OK) return st;
+  if (y->dtype != TC_F32) return TC_EDTYPE;
+  FftLayout L;
+  if ((st = fft_layout(x, k, mode, L)) != TC_OK) return st;
+  if (!is_contiguous(k) || y->ndim != 2) return TC_ESHAPE;
+  if (y->shape[0] != L.oshape[0] || y->shape[1] != L.oshape[1]) return TC_ESHAPE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (numel(y) == 0) return TC_OK;
+  if (numel(x) == 0 || numel(k) == 0) {
+    if (y->stride[1] == 1 && y->stride[0] == y->shape[1])
+      return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
+    return TC_ESHAPE;
+  }
+  if (!ws) return TC_EINVAL;
+  if (ws_bytes < L.total) return TC_ENOMEM;
+  char* w = static_cast<char*>(ws);
+  FftConv f{};
+  f.x = static_cast<const float*>(x->data);
+  f.xs0 = x->stride[0];
+  f.xs1 = x->stride[1];
+  f.H = (int)x->shape[0];
+  f.W = (int)x->shape[1];
+  f.k = static_cast<const float*>(k->data);
+  f.KH = (int)k->shape[0];
+  f.KW = (int)k->shape[1];
+  f.P = L.P;
+  f.Q = L.Q;
+  f.twP = reinterpret_cast<float2*>(w + L.twP);
+  f.twQ = reinterpret_cast<float2*>(w + L.twQ);
+  f.A = reinterpret_cast<float2*>(w + L.A);
+  f.B = reinterpret_cast<float2*>(w + L.B);
+  f.C = reinterpret_cast<float2*>(w + L.C);
+  f.y = static_cast<float*>(y->data);
+  f.ys0 = y->stride[0];
+  f.ys1 = y->stride[1];
+  f.OH = (int)y->shape[0];
+  f.OW = (int)y->shape[1];
+  f.o0 = (int)L.off[0];
+  f.o1 = (int)L.off[1];
+  return hip_status(launch_conv2d_fft(f, s));
+}
+
 // ============================================================================ pyramid / derivatives
 extern "C" int tc_pyramid_shape(int64_t H, int64_t W, int32_t level, int64_t* Hl, int64_t* Wl) {
   if (H < 0 || W < 0 || level < 0 || level > 62 || !Hl || !Wl) return TC_EINVAL;

@@ -1,0 +1,137 @@
+"""GPU parity of the FFT branch of 2-D convolution (tc_conv2d_fft) against the
+FP64 oracle's direct convolution, and of the hybrid dispatcher.
+
+Tolerance.  The FFT result carries a norm-wise error (every output mixes every
+input): for a radix-2 transform with accurate twiddles the relative 2-norm
+error of one N-point transform is at most log2(N) * eta with eta <= 8u
+(u = 2^-24; Higham, Accuracy and Stability of Numerical Algorithms, the FFT
+chapter).  The path transforms x and k forward (log2(PQ) stages each), takes
+one complex product per point and transforms back; with ||x (*) k||_2 <=
+||x||_2 ||k||_1 this gives
+
+    ||y - y64||_2 <= TAU_FFT ||x||_2 ||k||_1,   TAU_FFT = 3 * 8u * log2(PQ) + 4u,
+
+which the tests check, together with the element-wise consequence
+max |y - y64| <= ||y - y64||_2."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -24
+
+
+def tau_fft(xs, ks):
+    P = 2
+    while P < xs[0] + ks[0] - 1:
+        P *= 2
+    Q = 2
+    while Q < xs[1] + ks[1] - 1:
+        Q *= 2
+    return 3 * 8 * U * math.log2(P * Q) + 4 * U
+
+
+@pytest.fixture(scope="module")
+def api(gpu_lib):
+    from paper_1612_08825_amd import api
+
+    return api
+
+
+def check(x, k, y, ref):
+    err = np.asarray(y, dtype=np.float64) - ref
+    bound = tau_fft(x.shape, k.shape) * np.linalg.norm(x) * np.abs(k).sum()
+    e2 = float(np.linalg.norm(err))
+    assert e2 <= bound, (e2, bound)
+    return e2 / bound
+
+
+@pytest.mark.parametrize("xs,ks", [((37, 50), (5, 7)), ((20, 33), (15, 15)), ((3, 4), (6, 9)), ((64, 64), (64, 64)),
+                                   ((100, 300), (31, 31)), ((1, 1), (1, 1)), ((257, 129), (2, 40))])
+@pytest.mark.parametrize("mode", ["full", "same", "valid"])
+def test_fft_matches_oracle(api, xs, ks, mode):
+    ge = all(a >= b for a, b in zip(xs, ks))
+    le = all(a <= b for a, b in zip(xs, ks))
+    if mode == "valid" and not (ge or le):
+        pytest.skip("valid mode needs x >= k or x <= k in every dimension")
+    rng = np.random.default_rng(sum(xs) + 7 * sum(ks))
+    x = rng.normal(0, 1, xs).astype(np.float32)
+    k = rng.normal(0, 1, ks).astype(np.float32)
+    y = api.conv2d_fft(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode)
+    torch.cuda.synchronize()
+    ref = O.conv(x.astype(np.float64), k.astype(np.float64), mode)
+    assert tuple(y.shape) == ref.shape
+    r = check(x, k, y.cpu().numpy(), ref)
+    print(f"[fft] {xs}*{ks} {mode}: error / bound {r:.3f}")
+
+
+def test_fft_large_against_direct_and_sampled_oracle(api):
+    """2048 x 2048 image, 31 x 31 kernel (the size the hybrid switches at):
+    against the direct kernels (pinned element-wise elsewhere) and sampled
+    oracle outputs."""
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, (2048, 2048)).astype(np.float32)
+    k = rng.normal(0, 1, (31, 31)).astype(np.float32)
+    xd, kd = torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda()
+    yf = api.conv2d_fft(xd, kd, "full")
+    yd = api.conv_nd(xd, kd, "full")
+    torch.cuda.synchronize()
+    bound = tau_fft(x.shape, k.shape) * np.linalg.norm(x) * np.abs(k).sum()
+    diff = (yf.double() - yd.double()).cpu().numpy()
+    assert float(np.linalg.norm(diff)) <= bound
+    idx = [(0, 0), (15, 15), (1000, 1234), (2077, 2077), (2060, 5), (30, 2070)]
+    want = O.conv_at(x, k, "full", idx)
+    got = yf.cpu().numpy()
+    for (i, j), w in zip(idx, want):
+        assert abs(float(got[i, j]) - float(w)) <= bound, (i, j)
+
+
+def test_hybrid_dispatch(api):
+    x = torch.randn(200, 300, device="cuda")
+    small = torch.randn(5, 5, device="cuda")
+    big = torch.randn(41, 41, device="cuda")
+    a = api.conv2d_hybrid(x, small, "same")
+    b = api.conv_nd(x, small, "same")
+    c = api.conv2d_hybrid(x, big, "same")
+    d = api.conv2d_fft(x, big, "same")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(c, d)
+
+
+def test_strided_input_output(api):
+    rng = np.random.default_rng(8)
+    x = rng.normal(0, 1, (60, 90)).astype(np.float32)
+    k = rng.normal(0, 1, (9, 5)).astype(np.float32)
+    xt = torch.from_numpy(np.ascontiguousarray(x.T)).cuda().t()  # column-major view
+    yb = torch.full((68 + 4, 2 * 94), -5.0, device="cuda")
+    yv = yb[2:70, ::2]
+    api.conv2d_fft(xt, torch.from_numpy(k).cuda(), "full", out=yv)
+    torch.cuda.synchronize()
+    check(x, k, yv.cpu().numpy(), O.conv(x.astype(np.float64), k.astype(np.float64), "full"))
+    assert bool((yb[:2] == -5).all()) and bool((yb[70:] == -5).all()) and bool((yb[:, 1::2] == -5).all())
+
+
+def test_rejections(api):
+    from paper_1612_08825_amd import _lib as L
+    import ctypes as C
+
+    lib = api._lib()
+    n = C.c_size_t(0)
+    big = torch.zeros((4000, 10), device="cuda")
+    k = torch.zeros((200, 3), device="cuda")
+    assert lib.tc_conv2d_fft_workspace_size(C.byref(api._desc(big)), C.byref(api._desc(k)), L.MODES["full"],
+                                            C.byref(n)) == L.TC_ESHAPE
+    h = torch.zeros((10, 10), dtype=torch.float16, device="cuda")
+    assert lib.tc_conv2d_fft_workspace_size(C.byref(api._desc(h)), C.byref(api._desc(k)), L.MODES["full"],
+                                            C.byref(n)) == L.TC_EDTYPE
+    x = torch.zeros((10, 10), device="cuda")
+    kk = torch.zeros((3, 3), device="cuda")
+    y = torch.zeros((12, 12), device="cuda")
+    ws = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    assert lib.tc_conv2d_fft(C.byref(api._desc(x)), C.byref(api._desc(kk)), L.MODES["full"], C.byref(api._desc(y)),
+                             C.c_void_p(ws.data_ptr()), 64, None) == L.TC_ENOMEM
