@@ -134,8 +134,10 @@ def conv_nd_auto(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Opti
 SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
 
 # Kernel side length from which the FFT branch beats the direct kernels on
-# MI355X (2048 x 2048 FP32 images, full mode; bench.py's crossover sweep).
-FFT_THRESHOLD = 31
+# MI355X (2048 x 2048 FP32 images, full mode, square kernels; bench.py's
+# crossover sweep: direct 0.98 ms against FFT 1.25 ms at 39, 1.56 against 1.25
+# at 47).
+FFT_THRESHOLD = 43
 
 
 def conv2d_fft_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full") -> int:

@@ -13,8 +13,9 @@
 //     For rank 3 the grid's z dimension is the output plane, and the kernel
 //     loops over the kernel's planes, re-staging the matching input plane.
 //   * conv_generic: one thread per output element of any rank <= 8.
-// The tiled and generic kernels visit taps in kernel-row-major order for every
-// output element; conv2d_rows visits tap rows from last to first.
+// The generic kernel visits taps in kernel-row-major order for every output
+// element, the tiled kernel kernel rows first to last and the taps within a
+// row last to first; conv2d_rows visits tap rows from last to first.
 #include <type_traits>
 
 #include "device_common.hpp"
@@ -88,9 +89,12 @@ __device__ __forceinline__ void tile_fma(TA (&acc)[kRY][kRX], const TA* lds, con
                                          int KW) {
   const int tx = threadIdx.x, ty = threadIdx.y;
   for (int ky = 0; ky < KH; ++ky) {
+    // the taps of kernel row ky from last to first, kt[j] = k[ky][KW - 1 - j],
+    // so that output column rx meets input column rx + j of the window (a
+    // static register index for every j)
     TA kt[KWMAX];
 #pragma unroll
-    for (int kx = 0; kx < KWMAX; ++kx) kt[kx] = (kx < KW) ? load_k<TA>(k, kp_off + ky * KW + kx) : (TA)0;
+    for (int j = 0; j < KWMAX; ++j) kt[j] = (j < KW) ? load_k<TA>(k, kp_off + ky * KW + (KW - 1 - j)) : (TA)0;
 #pragma unroll
     for (int ry = 0; ry < kRY; ++ry) {
       const TA* row = lds + (ty * kRY + ry + (KH - 1 - ky)) * PITCH + tx * kRX;
@@ -98,10 +102,10 @@ __device__ __forceinline__ void tile_fma(TA (&acc)[kRY][kRX], const TA* lds, con
 #pragma unroll
       for (int c = 0; c < kRX + KWMAX - 1; ++c) v[c] = row[c];
 #pragma unroll
-      for (int kx = 0; kx < KWMAX; ++kx) {
-        if (kx < KW) {
+      for (int j = 0; j < KWMAX; ++j) {
+        if (j < KW) {
 #pragma unroll
-          for (int rx = 0; rx < kRX; ++rx) acc[ry][rx] = mac<TA>(acc[ry][rx], kt[kx], v[rx + KW - 1 - kx]);
+          for (int rx = 0; rx < kRX; ++rx) acc[ry][rx] = mac<TA>(acc[ry][rx], kt[j], v[rx + j]);
         }
       }
     }
@@ -219,6 +223,8 @@ hipError_t launch_tiled_t(const Tile2D& t, int kwmax, dim3 grid, hipStream_t s) 
     case 4: return go(conv2d_tiled<TX, 4>, ((kTileX + 4 - 1 + 3) / 4) * 4);
     case 8: return go(conv2d_tiled<TX, 8>, ((kTileX + 8 - 1 + 3) / 4) * 4);
     case 16: return go(conv2d_tiled<TX, 16>, ((kTileX + 16 - 1 + 3) / 4) * 4);
+    case 32: return go(conv2d_tiled<TX, 32>, ((kTileX + 32 - 1 + 3) / 4) * 4);
+    case 64: return go(conv2d_tiled<TX, 64>, ((kTileX + 64 - 1 + 3) / 4) * 4);
     default: return hipErrorInvalidValue;
   }
 }
@@ -867,9 +873,11 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
     return launch_rows(ra, (int)c.kshape[r - 2], s);
   }
 
-  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 16
-  // taps and kernel heights that keep the staged tile within 64 KiB of LDS.
-  const bool tiled_ok = (r == 2 || r == 3) && small_taps && c.kshape[r - 1] <= 16 && c.kshape[r - 2] <= 64 &&
+  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 32
+  // taps with up to 64 rows, or up to 64 taps with up to 48 rows, which keeps
+  // the staged tile within 64 KiB of LDS (127 x 96 or 111 x 128 elements).
+  const int64_t kh = c.kshape[r - 2], kw = c.kshape[r - 1];
+  const bool tiled_ok = (r == 2 || r == 3) && small_taps && ((kw <= 32 && kh <= 64) || (kw <= 64 && kh <= 48)) &&
                         c.xshape[r - 1] < (1LL << 30) && c.xshape[r - 2] < (1LL << 30) &&
                         c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&
                         c.off[r - 1] < (1LL << 30) && c.off[r - 2] < (1LL << 30) &&
@@ -906,7 +914,7 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
       t.OD = 1;
       t.offd = 0;
     }
-    const int kwmax = t.KW <= 4 ? 4 : (t.KW <= 8 ? 8 : 16);
+    const int kwmax = t.KW <= 4 ? 4 : t.KW <= 8 ? 8 : t.KW <= 16 ? 16 : t.KW <= 32 ? 32 : 64;
     const dim3 grid((unsigned)((t.OW + kTileX - 1) / kTileX), (unsigned)((t.OH + kTileY - 1) / kTileY),
                     (unsigned)t.OD);
     return launch_tiled(c.xdt, t, kwmax, grid, s);

@@ -41,7 +41,11 @@ SHAPES_2D = [((70, 130), (3, 3)), ((129, 65), (7, 7)), ((100, 77), (15, 15)), ((
              ((64, 64), (1, 1)), ((1, 200), (1, 5)), ((67, 67), (2, 5)), ((40, 33), (16, 16)), ((33, 19), (20, 3)),
              # several bands and 256-column waves with ragged tails (interior items take the unchecked path)
              ((61, 777), (3, 3)), ((45, 600), (2, 2)), ((37, 530), (5, 5)), ((29, 1100), (7, 7)), ((3, 5), (5, 5)),
-             ((70, 560), (15, 15)), ((9, 300), (15, 15))]
+             ((70, 560), (15, 15)), ((9, 300), (15, 15)),
+             # the 32-wide tiled kernel (kernel rows of 17..32 taps)
+             ((150, 140), (23, 23)), ((80, 200), (17, 31)), ((70, 66), (64, 32)), ((20, 25), (31, 31)),
+             # the 64-wide tiled kernel (rows of 33..64 taps, at most 48 rows)
+             ((90, 150), (47, 47)), ((40, 300), (48, 64)), ((66, 70), (33, 40))]
 
 
 @pytest.mark.parametrize("xs,ks", SHAPES_2D)
@@ -57,7 +61,7 @@ def test_conv2d_f32(api, xs, ks, mode):
     _check_float(y, x, k, mode, f"f32 {xs}*{ks} {mode}")
 
 
-@pytest.mark.parametrize("xs,ks", SHAPES_2D[:5])
+@pytest.mark.parametrize("xs,ks", SHAPES_2D[:5] + SHAPES_2D[-7:-5] + SHAPES_2D[-3:-2])
 @pytest.mark.parametrize("mode", ["full", "valid"])
 def test_conv2d_u8_exact(api, xs, ks, mode):
     try:
