@@ -132,7 +132,7 @@ int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, const tc_tensor
  * route the paper's hybrid FastConv takes for kernels above a size threshold
  * (Accelerating Convolutions).  The result, modes and output extents are those
  * of tc_conv_nd for 2-D F32 x and k; x and k are zero-padded to P x Q, the
- * powers of two >= (H+KH-1) x (W+KW-1), transformed (radix-2 Stockham, FP32,
+ * powers of two >= (H+KH-1) x (W+KW-1), transformed (radix-4 Stockham, FP32,
  * twiddles from sincospi), multiplied, transformed back and cut to the mode.
  * P and Q are at most 4096 (TC_ESHAPE beyond).  x and y may be strided; k is
  * contiguous device memory.  ws: device workspace of

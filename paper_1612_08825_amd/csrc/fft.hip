@@ -2,14 +2,12 @@
 // y = F^-1(F(x) F(k)); Accelerating Convolutions: the hybrid that switches to
 // it for large kernels).
 //
-// fft_twiddles: w[k] = exp(-2 pi i k / N), k < N/2, with sincospi (exact
+// fft_twiddles: w[k] = exp(-2 pi i k / N), k < N, with sincospi (exact
 //               argument k/N for N a power of two).
-// fft_rows:     radix-2 Stockham transform of length N = 2^m <= 4096 along each
-//               row, one work-group per row, the row held in LDS; stage s
-//               (sub-transform length L = 2^(s+1)) maps a = v[j], b = v[j + N/2]
-//               to v'[(j >> s) L + k] = a + w b and v'[(j >> s) L + k + L/2] =
-//               a - w b, k = j mod L/2, w = exp(-+2 pi i k / L).  The inverse
-//               uses conjugate twiddles and no scale.
+// fft_rows:     Stockham transform of length N = 2^m <= 4096 along each row,
+//               one work-group per row, the row held in LDS: one radix-2
+//               stage when m is odd, then radix-4 stages (described in the
+//               kernel).  The inverse uses conjugate twiddles and no scale.
 // transpose_c:  complex R x C -> C x R through 32 x 33 LDS tiles.
 // pad_real, mul_c, extract_real: the zero-padded complex images, the
 //               pointwise product, and the real part scaled by 1/(P Q) and cut
@@ -23,14 +21,21 @@ namespace ttc {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftPerThread = kFftMaxN / 2 / kFftThreads;  // butterflies per thread per stage (max)
+constexpr int kFftPerThread = kFftMaxN / 2 / kFftThreads;   // radix-2 butterflies per thread (max)
+constexpr int kFftPerThread4 = kFftMaxN / 4 / kFftThreads;  // radix-4 butterflies per thread (max)
 
 __global__ __launch_bounds__(256) void fft_twiddles(float2* __restrict__ tw, int N) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N / 2) return;
+  if (k >= N) return;
   float s, c;
   sincospif(-2.0f * (float)k / (float)N, &s, &c);
   tw[k] = make_float2(c, s);
+}
+
+template <bool INV>
+__device__ __forceinline__ float2 cmul_tw(float2 w, float2 b) {
+  if (INV) w.y = -w.y;
+  return make_float2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
 }
 
 template <bool INV>
@@ -41,21 +46,18 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += kFftThreads) buf[i] = row[i];
   __syncthreads();
-  const int half = N >> 1;
-  for (int s = 0; s < m; ++s) {
-    const int Ls = 1 << s;
+  int lg = 0;  // log2 of the sub-transform length done so far
+  if (m & 1) {
+    // one radix-2 stage (sub-length 1: no twiddles)
+    const int half = N >> 1;
     float2 o0[kFftPerThread], o1[kFftPerThread];
 #pragma unroll
     for (int c = 0; c < kFftPerThread; ++c) {
       const int j = tid + c * kFftThreads;
       if (j < half) {
-        const int k = j & (Ls - 1);
         const float2 a = buf[j], b = buf[j + half];
-        float2 w = tw[k << (m - 1 - s)];
-        if (INV) w.y = -w.y;
-        const float2 wb = make_float2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
-        o0[c] = make_float2(a.x + wb.x, a.y + wb.y);
-        o1[c] = make_float2(a.x - wb.x, a.y - wb.y);
+        o0[c] = make_float2(a.x + b.x, a.y + b.y);
+        o1[c] = make_float2(a.x - b.x, a.y - b.y);
       }
     }
     __syncthreads();
@@ -63,10 +65,49 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
     for (int c = 0; c < kFftPerThread; ++c) {
       const int j = tid + c * kFftThreads;
       if (j < half) {
+        buf[2 * j] = o0[c];
+        buf[2 * j + 1] = o1[c];
+      }
+    }
+    __syncthreads();
+    lg = 1;
+  }
+  // radix-4 stages: sub-length Ls = 2^lg; a_t = v[j + t N/4] w^(t k),
+  // w = exp(-+2 pi i / (4 Ls)) = tw[k t N / (4 Ls)], k = j mod Ls; the 4-point
+  // transform of (a_0..a_3) goes to v'[(j / Ls) 4 Ls + k + q Ls], q = 0..3
+  const int q4 = N >> 2;
+  for (; lg < m; lg += 2) {
+    const int Ls = 1 << lg;
+    const int tws = m - lg - 2;  // log2(N / (4 Ls))
+    float2 o[kFftPerThread4][4];
+#pragma unroll
+    for (int c = 0; c < kFftPerThread4; ++c) {
+      const int j = tid + c * kFftThreads;
+      if (j < q4) {
         const int k = j & (Ls - 1);
-        const int base = ((j >> s) << (s + 1)) + k;
-        buf[base] = o0[c];
-        buf[base + Ls] = o1[c];
+        const float2 a0 = buf[j];
+        const float2 a1 = cmul_tw<INV>(tw[k << tws], buf[j + q4]);
+        const float2 a2 = cmul_tw<INV>(tw[(2 * k) << tws], buf[j + 2 * q4]);
+        const float2 a3 = cmul_tw<INV>(tw[(3 * k) << tws], buf[j + 3 * q4]);
+        const float2 b0 = make_float2(a0.x + a2.x, a0.y + a2.y), b1 = make_float2(a0.x - a2.x, a0.y - a2.y);
+        const float2 b2 = make_float2(a1.x + a3.x, a1.y + a3.y), b3 = make_float2(a1.x - a3.x, a1.y - a3.y);
+        // forward: -i b3; inverse: +i b3
+        const float2 r = INV ? make_float2(-b3.y, b3.x) : make_float2(b3.y, -b3.x);
+        o[c][0] = make_float2(b0.x + b2.x, b0.y + b2.y);
+        o[c][1] = make_float2(b1.x + r.x, b1.y + r.y);
+        o[c][2] = make_float2(b0.x - b2.x, b0.y - b2.y);
+        o[c][3] = make_float2(b1.x - r.x, b1.y - r.y);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kFftPerThread4; ++c) {
+      const int j = tid + c * kFftThreads;
+      if (j < q4) {
+        const int k = j & (Ls - 1);
+        const int base = ((j >> lg) << (lg + 2)) + k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) buf[base + q * Ls] = o[c][q];
       }
     }
     __syncthreads();
@@ -158,8 +199,8 @@ hipError_t forward2d(const float* x, int64_t s0, int64_t s1, int H, int W, int P
 hipError_t launch_conv2d_fft(const FftConv& f, hipStream_t s) {
   const int P = f.P, Q = f.Q;
   hipError_t e;
-  hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((P / 2 + 255) / 256)), dim3(256), 0, s, f.twP, P);
-  hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((Q / 2 + 255) / 256)), dim3(256), 0, s, f.twQ, Q);
+  hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, f.twP, P);
+  hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, f.twQ, Q);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = forward2d(f.x, f.xs0, f.xs1, f.H, f.W, P, Q, f.twP, f.twQ, f.A, f.B, s)) != hipSuccess) return e;
   if ((e = forward2d(f.k, f.KW, 1, f.KH, f.KW, P, Q, f.twP, f.twQ, f.A, f.C, s)) != hipSuccess) return e;

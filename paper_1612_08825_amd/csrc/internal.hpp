@@ -45,7 +45,7 @@ hipError_t launch_conv_separable(const SepConv& c, hipStream_t s);
 
 // FFT branch of 2-D FP32 convolution: x (H x W, strided) and k (KH x KW,
 // contiguous) zero-padded to P x Q (powers of two, <= kFftMaxN); twiddle
-// tables twP (P/2) and twQ (Q/2); A is P x Q, B and C are Q x P complex
+// tables twP (P entries) and twQ (Q); A is P x Q, B and C are Q x P complex
 // scratch; the output y (OH x OW, strided) is full index n + (o0, o1).
 constexpr int kFftMaxN = 4096;
 struct FftConv {

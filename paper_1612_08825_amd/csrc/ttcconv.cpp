@@ -316,9 +316,9 @@ int fft_layout(const tc_tensor* x, const tc_tensor* k, int32_t mode, FftLayout& 
   L.Q = pow2_at_least(fw);
   size_t o = 0;
   L.twP = o;
-  o += fft_align((size_t)(L.P / 2) * sizeof(float2));
+  o += fft_align((size_t)L.P * sizeof(float2));
   L.twQ = o;
-  o += fft_align((size_t)(L.Q / 2) * sizeof(float2));
+  o += fft_align((size_t)L.Q * sizeof(float2));
   const size_t plane = fft_align((size_t)L.P * L.Q * sizeof(float2));
   L.A = o;
   L.B = o + plane;

@@ -2,7 +2,7 @@
 FP64 oracle's direct convolution, and of the hybrid dispatcher.
 
 Tolerance.  The FFT result carries a norm-wise error (every output mixes every
-input): for a radix-2 transform with accurate twiddles the relative 2-norm
+input): for a radix-2 or radix-4 transform with accurate twiddles the relative 2-norm
 error of one N-point transform is at most log2(N) * eta with eta <= 8u
 (u = 2^-24; Higham, Accuracy and Stability of Numerical Algorithms, the FFT
 chapter).  The path transforms x and k forward (log2(PQ) stages each), takes
@@ -93,8 +93,8 @@ def test_fft_large_against_direct_and_sampled_oracle(api):
 
 def test_hybrid_dispatch(api):
     x = torch.randn(200, 300, device="cuda")
-    small = torch.randn(5, 5, device="cuda")
-    big = torch.randn(41, 41, device="cuda")
+    small = torch.randn(api.FFT_THRESHOLD - 2, 5, device="cuda")
+    big = torch.randn(api.FFT_THRESHOLD, 3, device="cuda")
     a = api.conv2d_hybrid(x, small, "same")
     b = api.conv_nd(x, small, "same")
     c = api.conv2d_hybrid(x, big, "same")
