@@ -119,40 +119,44 @@ __global__ __launch_bounds__(256) void conv2d_tiled(Tile2D a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* lds = reinterpret_cast<TA*>(smem_raw);
 
-  const int o0 = blockIdx.y * kTileY;
-  const int p0 = blockIdx.x * kTileX;
-  const int od = blockIdx.z;  // output plane (0 for 2-D)
-  const int rows = kTileY + a.KH - 1;
-  const int cols = kTileX + a.KW - 1;
-  const int r0 = o0 + a.off0 - (a.KH - 1);
-  const int c0 = p0 + a.off1 - (a.KW - 1);
+  // tiles of output rows in steps of the grid's y extent (at most 65535)
+  const int n_ty = (a.OH + kTileY - 1) / kTileY;
+  for (int tile_y = blockIdx.y; tile_y < n_ty; tile_y += gridDim.y) {
+    const int o0 = tile_y * kTileY;
+    const int p0 = blockIdx.x * kTileX;
+    const int od = blockIdx.z;  // output plane (0 for 2-D)
+    const int rows = kTileY + a.KH - 1;
+    const int cols = kTileX + a.KW - 1;
+    const int r0 = o0 + a.off0 - (a.KH - 1);
+    const int c0 = p0 + a.off1 - (a.KW - 1);
 
-  TA acc[kRY][kRX];
+    TA acc[kRY][kRX];
 #pragma unroll
-  for (int i = 0; i < kRY; ++i)
+    for (int i = 0; i < kRY; ++i)
 #pragma unroll
-    for (int j = 0; j < kRX; ++j) acc[i][j] = (TA)0;
+      for (int j = 0; j < kRX; ++j) acc[i][j] = (TA)0;
 
-  const TX* x = reinterpret_cast<const TX*>(a.x);
-  const int nd = od + a.offd;  // full plane index
-  for (int kd = 0; kd < a.KD; ++kd) {
-    const int xd = nd - kd;
-    if (xd < 0 || xd >= a.D) continue;  // uniform across the work-group
-    __syncthreads();
-    stage_tile<TX, PITCH>(lds, x + (int64_t)xd * a.xsd, a, r0, c0, rows, cols);
-    __syncthreads();
-    tile_fma<TA, KWMAX, PITCH>(acc, lds, a.k, kd * a.KH * a.KW, a.KH, a.KW);
-  }
+    const TX* x = reinterpret_cast<const TX*>(a.x);
+    const int nd = od + a.offd;  // full plane index
+    for (int kd = 0; kd < a.KD; ++kd) {
+      const int xd = nd - kd;
+      if (xd < 0 || xd >= a.D) continue;  // uniform across the work-group
+      __syncthreads();
+      stage_tile<TX, PITCH>(lds, x + (int64_t)xd * a.xsd, a, r0, c0, rows, cols);
+      __syncthreads();
+      tile_fma<TA, KWMAX, PITCH>(acc, lds, a.k, kd * a.KH * a.KW, a.KH, a.KW);
+    }
 
-  TA* y = reinterpret_cast<TA*>(a.y) + (int64_t)od * a.ysd;
+    TA* y = reinterpret_cast<TA*>(a.y) + (int64_t)od * a.ysd;
 #pragma unroll
-  for (int ry = 0; ry < kRY; ++ry) {
-    const int o = o0 + threadIdx.y * kRY + ry;
-    if (o >= a.OH) continue;
+    for (int ry = 0; ry < kRY; ++ry) {
+      const int o = o0 + threadIdx.y * kRY + ry;
+      if (o >= a.OH) continue;
 #pragma unroll
-    for (int rx = 0; rx < kRX; ++rx) {
-      const int p = p0 + threadIdx.x * kRX + rx;
-      if (p < a.OW) y[(int64_t)o * a.ys0 + (int64_t)p * a.ys1] = acc[ry][rx];
+      for (int rx = 0; rx < kRX; ++rx) {
+        const int p = p0 + threadIdx.x * kRX + rx;
+        if (p < a.OW) y[(int64_t)o * a.ys0 + (int64_t)p * a.ys1] = acc[ry][rx];
+      }
     }
   }
 }
@@ -915,7 +919,8 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
       t.offd = 0;
     }
     const int kwmax = t.KW <= 4 ? 4 : t.KW <= 8 ? 8 : t.KW <= 16 ? 16 : t.KW <= 32 ? 32 : 64;
-    const dim3 grid((unsigned)((t.OW + kTileX - 1) / kTileX), (unsigned)((t.OH + kTileY - 1) / kTileY),
+    const int64_t n_ty = (t.OH + kTileY - 1) / kTileY;
+    const dim3 grid((unsigned)((t.OW + kTileX - 1) / kTileX), (unsigned)(n_ty < 65535 ? n_ty : 65535),
                     (unsigned)t.OD);
     return launch_tiled(c.xdt, t, kwmax, grid, s);
   }

@@ -34,19 +34,20 @@ constexpr int kSumThreads = 256;
 __global__ __launch_bounds__(256) void lowpass3(const float* __restrict__ src, int H, int W,
                                                  float* __restrict__ dst) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
   if (j >= W) return;
   const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < W ? j + 1 : W - 1;
-  float acc = 0.f;
   const float wr[3] = {0.25f, 0.5f, 0.25f};
+  for (int i = blockIdx.y; i < H; i += gridDim.y) {
+    float acc = 0.f;
 #pragma unroll
-  for (int a = -1; a <= 1; ++a) {
-    const int r = min(max(i + a, 0), H - 1);
-    const float* row = src + (int64_t)r * W;
-    const float h = 0.25f * row[jm] + 0.5f * row[j] + 0.25f * row[jp];
-    acc += wr[a + 1] * h;
+    for (int a = -1; a <= 1; ++a) {
+      const int r = min(max(i + a, 0), H - 1);
+      const float* row = src + (int64_t)r * W;
+      const float h = 0.25f * row[jm] + 0.5f * row[j] + 0.25f * row[jp];
+      acc += wr[a + 1] * h;
+    }
+    dst[(int64_t)i * W + j] = acc;
   }
-  dst[(int64_t)i * W + j] = acc;
 }
 
 struct Plane {
@@ -201,7 +202,8 @@ int variant_sum_blocks(int64_t positions) {
 
 hipError_t launch_lowpass3(const float* src, int H, int W, float* dst, hipStream_t s) {
   if (H <= 0 || W <= 0) return hipSuccess;
-  hipLaunchKernelGGL(lowpass3, dim3((unsigned)((W + 255) / 256), (unsigned)H), dim3(256), 0, s, src, H, W, dst);
+  const unsigned gy = (unsigned)(H < 65535 ? H : 65535);
+  hipLaunchKernelGGL(lowpass3, dim3((unsigned)((W + 255) / 256), gy), dim3(256), 0, s, src, H, W, dst);
   return hipGetLastError();
 }
 
