@@ -42,9 +42,13 @@ template <bool INV>
 __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ data, int64_t row_stride, int N, int m,
                                                         const float2* __restrict__ tw) {
   __shared__ float2 buf[kFftMaxN];
+  // every radix-4 stage reads w^k = tw[k N / (4 Ls)] with k < Ls: the first
+  // quarter of the table, staged in LDS once
+  __shared__ float2 twl[kFftMaxN / 4];
   float2* row = data + (int64_t)blockIdx.x * row_stride;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += kFftThreads) buf[i] = row[i];
+  for (int i = tid; i < (N >> 2); i += kFftThreads) twl[i] = tw[i];
   __syncthreads();
   int lg = 0;  // log2 of the sub-transform length done so far
   if (m & 1) {
@@ -85,10 +89,14 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
       const int j = tid + c * kFftThreads;
       if (j < q4) {
         const int k = j & (Ls - 1);
+        // one table read per butterfly: w^2k and w^3k as products of w^k
+        const float2 w1 = twl[k << tws];
+        const float2 w2 = make_float2(w1.x * w1.x - w1.y * w1.y, 2.f * w1.x * w1.y);
+        const float2 w3 = make_float2(w2.x * w1.x - w2.y * w1.y, w2.x * w1.y + w2.y * w1.x);
         const float2 a0 = buf[j];
-        const float2 a1 = cmul_tw<INV>(tw[k << tws], buf[j + q4]);
-        const float2 a2 = cmul_tw<INV>(tw[(2 * k) << tws], buf[j + 2 * q4]);
-        const float2 a3 = cmul_tw<INV>(tw[(3 * k) << tws], buf[j + 3 * q4]);
+        const float2 a1 = cmul_tw<INV>(w1, buf[j + q4]);
+        const float2 a2 = cmul_tw<INV>(w2, buf[j + 2 * q4]);
+        const float2 a3 = cmul_tw<INV>(w3, buf[j + 3 * q4]);
         const float2 b0 = make_float2(a0.x + a2.x, a0.y + a2.y), b1 = make_float2(a0.x - a2.x, a0.y - a2.y);
         const float2 b2 = make_float2(a1.x + a3.x, a1.y + a3.y), b3 = make_float2(a1.x - a3.x, a1.y - a3.y);
         // forward: -i b3; inverse: +i b3
