@@ -415,8 +415,23 @@ def variant_ablation(api, torch, np):
             one_pass()
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
+            # the same launches replayed from a HIP graph: kernel time without the host's per-call cost
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                one_pass()
+            g.replay()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ms_graph = e0.elapsed_time(e1)
+            del g
             recs, picks = api.decode_levels(lv), api.decode_picks(pk)
-            row = {"ms_per_pair": round(ms / n, 4), "Gpixel_per_s": round(n * H * W / (ms * 1e-3) / 1e9, 3)}
+            row = {"ms_per_pair": round(ms / n, 4), "Gpixel_per_s": round(n * H * W / (ms * 1e-3) / 1e9, 3),
+                   "ms_per_pair_graph": round(ms_graph / n, 4),
+                   "Gpixel_per_s_graph": round(n * H * W / (ms_graph * 1e-3) / 1e9, 3)}
             for l in range(LEVELS):
                 r = recs[l::LEVELS]
                 ok = r["status"] == 0

@@ -18,8 +18,9 @@
 //                  x = 2^l (j + 1/2) - W0/2, 1 <= i <= H_l - 2, 1 <= j <= W_l - 2
 //                (Convolutions section: the centred 3x3 masks)
 //   Spatial derivatives are per base pixel (divided by 2^l).
-// variant_finish: per level the block partials in a fixed order (FP64), the
-//                3x3 solve, and the multi-scale choice by the decreasing-TTC rule.
+// variant_finish: per level (one wave each) the block partials in a fixed
+//                order (FP64), the 3x3 solve, and the multi-scale choice by the
+//                decreasing-TTC rule.
 #include <math.h>
 
 #include "device_common.hpp"
@@ -139,22 +140,30 @@ __global__ __launch_bounds__(kSumThreads) void stencil_sums(Plane a, Plane b, in
   }
 }
 
-__global__ __launch_bounds__(64) void variant_finish(const double* __restrict__ part, VariantLevels lv,
-                                                     tc_ttc_level* __restrict__ out, tc_ttc_pick* __restrict__ pick) {
+__global__ __launch_bounds__(64 * TC_MAX_LEVELS) void variant_finish(const double* __restrict__ part, VariantLevels lv,
+                                                                     tc_ttc_level* __restrict__ out,
+                                                                     tc_ttc_pick* __restrict__ pick) {
   __shared__ tc_ttc_level res[TC_MAX_LEVELS];
-  const int l = threadIdx.x;
+  const int l = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (l < lv.levels) {
+    // wave l: each lane adds every 64th block's partials, then a fixed butterfly
     double s[10];
+#pragma unroll
     for (int q = 0; q < 10; ++q) s[q] = 0.0;
     const double* p = part + lv.part_off[l] * 10;
-    for (int bk = 0; bk < lv.blocks[l]; ++bk)
+    for (int bk = lane; bk < lv.blocks[l]; bk += 64)
+#pragma unroll
       for (int q = 0; q < 10; ++q) s[q] += p[(int64_t)bk * 10 + q];
-    tc_ttc_level r;
-    solve_level(s, r);
-    r.n = lv.n[l];
-    r.level = l;
-    res[l] = r;
-    out[l] = r;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) s[q] = wave_sum(s[q]);
+    if (lane == 0) {
+      tc_ttc_level r;
+      solve_level(s, r);
+      r.n = lv.n[l];
+      r.level = l;
+      res[l] = r;
+      out[l] = r;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -196,8 +205,8 @@ hipError_t sums_t(int stencil, const Image2D& a, const Image2D& b, int Hl, int W
 }  // namespace
 
 int variant_sum_blocks(int64_t positions) {
-  const int64_t b = (positions + 4 * kSumThreads - 1) / (4 * kSumThreads);
-  return (int)(b < 1 ? 1 : b > 1024 ? 1024 : b);
+  const int64_t b = (positions + 2 * kSumThreads - 1) / (2 * kSumThreads);
+  return (int)(b < 1 ? 1 : b > 2048 ? 2048 : b);
 }
 
 hipError_t launch_lowpass3(const float* src, int H, int W, float* dst, hipStream_t s) {
@@ -219,7 +228,7 @@ hipError_t launch_stencil_sums(int stencil, const Image2D& a, const Image2D& b, 
 
 hipError_t launch_variant_finish(const double* part, const VariantLevels& lv, tc_ttc_level* out, tc_ttc_pick* pick,
                                  hipStream_t s) {
-  hipLaunchKernelGGL(variant_finish, dim3(1), dim3(64), 0, s, part, lv, out, pick);
+  hipLaunchKernelGGL(variant_finish, dim3(1), dim3(64 * TC_MAX_LEVELS), 0, s, part, lv, out, pick);
   return hipGetLastError();
 }
 
