@@ -243,7 +243,7 @@ def fft_crossover(api, torch, steps):
     rng = np.random.default_rng(13)
     x = torch.from_numpy(rng.uniform(0, 1, (n, n)).astype(np.float32)).cuda()
     rows = []
-    for K in (7, 15, 17, 23, 31, 39, 43, 47, 63, 95):
+    for K in (7, 15, 17, 23, 31, 33, 35, 37, 39, 43, 47, 63, 95):
         k = torch.from_numpy(rng.normal(0, 1, (K, K)).astype(np.float32)).cuda()
         y = torch.empty((n + K - 1, n + K - 1), device="cuda")
         ws = torch.empty(api.conv2d_fft_workspace_size(x, k, "full"), dtype=torch.uint8, device="cuda")

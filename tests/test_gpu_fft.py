@@ -71,9 +71,9 @@ def test_fft_matches_oracle(api, xs, ks, mode):
 
 
 def test_fft_large_against_direct_and_sampled_oracle(api):
-    """2048 x 2048 image, 31 x 31 kernel (the size the hybrid switches at):
-    against the direct kernels (pinned element-wise elsewhere) and sampled
-    oracle outputs."""
+    """2048 x 2048 image, 31 x 31 kernel (near the size where the hybrid
+    switches): against the direct kernels (pinned element-wise elsewhere) and
+    sampled oracle outputs."""
     rng = np.random.default_rng(3)
     x = rng.uniform(0, 1, (2048, 2048)).astype(np.float32)
     k = rng.normal(0, 1, (31, 31)).astype(np.float32)
