@@ -135,10 +135,9 @@ SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
 
 # Kernel side length from which the FFT branch beats the direct kernels on
 # MI355X (2048 x 2048 FP32 images, full mode, square kernels; bench.py's
-# crossover sweep: direct 0.36 ms against FFT 0.74 ms at 31, 0.73 against 0.73
-# at 33 and 0.78 against 0.74 at 35, where the direct path moves from the 32-
-# to the 64-tap-wide tiled kernel).
-FFT_THRESHOLD = 33
+# crossover sweep: direct 0.73 ms against FFT 0.74 ms at 43, 0.80 against 0.74
+# at 47).
+FFT_THRESHOLD = 47
 
 
 def conv2d_fft_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full") -> int:

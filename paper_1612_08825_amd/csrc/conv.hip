@@ -228,6 +228,7 @@ hipError_t launch_tiled_t(const Tile2D& t, int kwmax, dim3 grid, hipStream_t s) 
     case 8: return go(conv2d_tiled<TX, 8>, ((kTileX + 8 - 1 + 3) / 4) * 4);
     case 16: return go(conv2d_tiled<TX, 16>, ((kTileX + 16 - 1 + 3) / 4) * 4);
     case 32: return go(conv2d_tiled<TX, 32>, ((kTileX + 32 - 1 + 3) / 4) * 4);
+    case 48: return go(conv2d_tiled<TX, 48>, ((kTileX + 48 - 1 + 3) / 4) * 4);
     case 64: return go(conv2d_tiled<TX, 64>, ((kTileX + 64 - 1 + 3) / 4) * 4);
     default: return hipErrorInvalidValue;
   }
@@ -877,11 +878,11 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
     return launch_rows(ra, (int)c.kshape[r - 2], s);
   }
 
-  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 32
+  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 48
   // taps with up to 64 rows, or up to 64 taps with up to 48 rows, which keeps
-  // the staged tile within 64 KiB of LDS (127 x 96 or 111 x 128 elements).
+  // the staged tile within 64 KiB of LDS (at most 127 x 112 or 111 x 128 elements).
   const int64_t kh = c.kshape[r - 2], kw = c.kshape[r - 1];
-  const bool tiled_ok = (r == 2 || r == 3) && small_taps && ((kw <= 32 && kh <= 64) || (kw <= 64 && kh <= 48)) &&
+  const bool tiled_ok = (r == 2 || r == 3) && small_taps && ((kw <= 48 && kh <= 64) || (kw <= 64 && kh <= 48)) &&
                         c.xshape[r - 1] < (1LL << 30) && c.xshape[r - 2] < (1LL << 30) &&
                         c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&
                         c.off[r - 1] < (1LL << 30) && c.off[r - 2] < (1LL << 30) &&
@@ -918,7 +919,7 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
       t.OD = 1;
       t.offd = 0;
     }
-    const int kwmax = t.KW <= 4 ? 4 : t.KW <= 8 ? 8 : t.KW <= 16 ? 16 : t.KW <= 32 ? 32 : 64;
+    const int kwmax = t.KW <= 4 ? 4 : t.KW <= 8 ? 8 : t.KW <= 16 ? 16 : t.KW <= 32 ? 32 : t.KW <= 48 ? 48 : 64;
     const int64_t n_ty = (t.OH + kTileY - 1) / kTileY;
     const dim3 grid((unsigned)((t.OW + kTileX - 1) / kTileX), (unsigned)(n_ty < 65535 ? n_ty : 65535),
                     (unsigned)t.OD);

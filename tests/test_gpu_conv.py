@@ -44,8 +44,9 @@ SHAPES_2D = [((70, 130), (3, 3)), ((129, 65), (7, 7)), ((100, 77), (15, 15)), ((
              ((70, 560), (15, 15)), ((9, 300), (15, 15)),
              # the 32-wide tiled kernel (kernel rows of 17..32 taps)
              ((150, 140), (23, 23)), ((80, 200), (17, 31)), ((70, 66), (64, 32)), ((20, 25), (31, 31)),
-             # the 64-wide tiled kernel (rows of 33..64 taps, at most 48 rows)
-             ((90, 150), (47, 47)), ((40, 300), (48, 64)), ((66, 70), (33, 40))]
+             # the 48- and 64-wide tiled kernels (rows of 33..48 taps with up to 64 rows,
+             # 49..64 taps with at most 48 rows)
+             ((90, 150), (47, 47)), ((40, 300), (48, 64)), ((66, 70), (33, 40)), ((100, 90), (64, 48))]
 
 
 @pytest.mark.parametrize("xs,ks", SHAPES_2D)
@@ -61,7 +62,7 @@ def test_conv2d_f32(api, xs, ks, mode):
     _check_float(y, x, k, mode, f"f32 {xs}*{ks} {mode}")
 
 
-@pytest.mark.parametrize("xs,ks", SHAPES_2D[:5] + SHAPES_2D[-7:-5] + SHAPES_2D[-3:-2])
+@pytest.mark.parametrize("xs,ks", SHAPES_2D[:5] + SHAPES_2D[-8:-6] + SHAPES_2D[-4:-3])
 @pytest.mark.parametrize("mode", ["full", "valid"])
 def test_conv2d_u8_exact(api, xs, ks, mode):
     try:
