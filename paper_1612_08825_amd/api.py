@@ -135,9 +135,9 @@ SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
 
 # Kernel side length from which the FFT branch beats the direct kernels on
 # MI355X (2048 x 2048 FP32 images, full mode, square kernels; bench.py's
-# crossover sweep: direct 0.73 ms against FFT 0.74 ms at 43, 0.80 against 0.74
-# at 47).
-FFT_THRESHOLD = 47
+# crossover sweep: direct 0.58 ms against FFT 0.59 ms at 35, 0.62 against 0.60
+# at 37).
+FFT_THRESHOLD = 37
 
 
 def conv2d_fft_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full") -> int:

@@ -9,9 +9,9 @@
 //               stage when m is odd, then radix-4 stages (described in the
 //               kernel).  The inverse uses conjugate twiddles and no scale.
 // transpose_c:  complex R x C -> C x R through 32 x 33 LDS tiles.
-// pad_real, mul_c, extract_real: the zero-padded complex images, the
-//               pointwise product, and the real part scaled by 1/(P Q) and cut
-//               to the requested mode.
+// mul_c:        the pointwise product.  The first forward pass reads the real
+//               image and pads it in LDS; the last inverse pass writes the real
+//               part, scaled by 1/(P Q), of the mode's window straight into y.
 #include <math.h>
 
 #include "device_common.hpp"
@@ -38,16 +38,36 @@ __device__ __forceinline__ float2 cmul_tw(float2 w, float2 b) {
   return make_float2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
 }
 
-template <bool INV>
+// Where a row pass reads and writes besides the complex plane: IN_REAL rows
+// come from a real H x W image (zero beyond it: the padding), OUT_REAL rows
+// o0 .. o0 + OH - 1 leave as the real part times `scale`, columns o1 .. o1 +
+// OW - 1, into y (the cut of the requested mode).
+struct RowIO {
+  const float* x;
+  int64_t xs0, xs1;
+  int H, W;
+  float* y;
+  int64_t ys0, ys1;
+  int OH, OW, o0, o1;
+  float scale;
+};
+
+template <bool INV, bool IN_REAL, bool OUT_REAL>
 __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ data, int64_t row_stride, int N, int m,
-                                                        const float2* __restrict__ tw) {
+                                                        const float2* __restrict__ tw, RowIO io) {
   __shared__ float2 buf[kFftMaxN];
   // every radix-4 stage reads w^k = tw[k N / (4 Ls)] with k < Ls: the first
   // quarter of the table, staged in LDS once
   __shared__ float2 twl[kFftMaxN / 4];
-  float2* row = data + (int64_t)blockIdx.x * row_stride;
+  const int r = OUT_REAL ? io.o0 + (int)blockIdx.x : (int)blockIdx.x;
+  float2* row = data + (int64_t)r * row_stride;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += kFftThreads) buf[i] = row[i];
+  if (IN_REAL) {
+    for (int i = tid; i < N; i += kFftThreads)
+      buf[i] = make_float2((r < io.H && i < io.W) ? io.x[(int64_t)r * io.xs0 + (int64_t)i * io.xs1] : 0.f, 0.f);
+  } else {
+    for (int i = tid; i < N; i += kFftThreads) buf[i] = row[i];
+  }
   for (int i = tid; i < (N >> 2); i += kFftThreads) twl[i] = tw[i];
   __syncthreads();
   int lg = 0;  // log2 of the sub-transform length done so far
@@ -120,7 +140,12 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
     }
     __syncthreads();
   }
-  for (int i = tid; i < N; i += kFftThreads) row[i] = buf[i];
+  if (OUT_REAL) {
+    float* yr = io.y + (int64_t)(r - io.o0) * io.ys0;
+    for (int i = tid; i < io.OW; i += kFftThreads) yr[(int64_t)i * io.ys1] = buf[io.o1 + i].x * io.scale;
+  } else {
+    for (int i = tid; i < N; i += kFftThreads) row[i] = buf[i];
+  }
 }
 
 // dst[c][r] = src[r][c] for an R x C source.
@@ -142,29 +167,11 @@ __global__ __launch_bounds__(256) void transpose_c(const float2* __restrict__ sr
   }
 }
 
-__global__ __launch_bounds__(256) void pad_real(const float* __restrict__ x, int64_t s0, int64_t s1, int H, int W,
-                                                float2* __restrict__ dst, int Q) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= Q) return;
-  const float v = (i < H && j < W) ? x[(int64_t)i * s0 + (int64_t)j * s1] : 0.f;
-  dst[(int64_t)i * Q + j] = make_float2(v, 0.f);
-}
-
 __global__ __launch_bounds__(256) void mul_c(float2* __restrict__ a, const float2* __restrict__ b, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float2 u = a[i], v = b[i];
   a[i] = make_float2(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
-}
-
-__global__ __launch_bounds__(256) void extract_real(const float2* __restrict__ src, int Q, int o0, int o1, int OH,
-                                                    int OW, float scale, float* __restrict__ y, int64_t y0,
-                                                    int64_t y1) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= OW) return;
-  y[(int64_t)i * y0 + (int64_t)j * y1] = src[(int64_t)(i + o0) * Q + (j + o1)].x * scale;
 }
 
 int ilog2(int n) {
@@ -173,14 +180,17 @@ int ilog2(int n) {
   return m;
 }
 
-hipError_t rows(float2* d, int n_rows, int N, const float2* tw, bool inv, hipStream_t s) {
-  if (inv)
-    hipLaunchKernelGGL(fft_rows<true>, dim3((unsigned)n_rows), dim3(kFftThreads), 0, s, d, (int64_t)N, N, ilog2(N),
-                       tw);
-  else
-    hipLaunchKernelGGL(fft_rows<false>, dim3((unsigned)n_rows), dim3(kFftThreads), 0, s, d, (int64_t)N, N, ilog2(N),
-                       tw);
+template <bool INV, bool IN_REAL, bool OUT_REAL>
+hipError_t rows_t(float2* d, int n_rows, int N, const float2* tw, const RowIO& io, hipStream_t s) {
+  hipLaunchKernelGGL((fft_rows<INV, IN_REAL, OUT_REAL>), dim3((unsigned)n_rows), dim3(kFftThreads), 0, s, d,
+                     (int64_t)N, N, ilog2(N), tw, io);
   return hipGetLastError();
+}
+
+hipError_t rows(float2* d, int n_rows, int N, const float2* tw, bool inv, hipStream_t s) {
+  const RowIO io{};
+  return inv ? rows_t<true, false, false>(d, n_rows, N, tw, io, s)
+             : rows_t<false, false, false>(d, n_rows, N, tw, io, s);
 }
 
 hipError_t transpose(const float2* src, int R, int C, float2* dst, hipStream_t s) {
@@ -193,11 +203,15 @@ hipError_t transpose(const float2* src, int R, int C, float2* dst, hipStream_t s
 // result is left transposed (Q x P) in `out`, `tmp` is P x Q scratch
 hipError_t forward2d(const float* x, int64_t s0, int64_t s1, int H, int W, int P, int Q, const float2* twP,
                      const float2* twQ, float2* tmp, float2* out, hipStream_t s) {
-  hipLaunchKernelGGL(pad_real, dim3((unsigned)((Q + 255) / 256), (unsigned)P), dim3(256), 0, s, x, s0, s1, H, W, tmp,
-                     Q);
+  RowIO io{};
+  io.x = x;
+  io.xs0 = s0;
+  io.xs1 = s1;
+  io.H = H;
+  io.W = W;
   hipError_t e;
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = rows(tmp, P, Q, twQ, false, s)) != hipSuccess) return e;
+  // the first pass reads the real image itself (zero-padded in LDS)
+  if ((e = rows_t<false, true, false>(tmp, P, Q, twQ, io, s)) != hipSuccess) return e;
   if ((e = transpose(tmp, P, Q, out, s)) != hipSuccess) return e;
   return rows(out, Q, P, twP, false, s);
 }
@@ -217,11 +231,19 @@ hipError_t launch_conv2d_fft(const FftConv& f, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = rows(f.B, Q, P, f.twP, true, s)) != hipSuccess) return e;
   if ((e = transpose(f.B, Q, P, f.A, s)) != hipSuccess) return e;
-  if ((e = rows(f.A, P, Q, f.twQ, true, s)) != hipSuccess) return e;
-  if (f.OH > 0 && f.OW > 0)
-    hipLaunchKernelGGL(extract_real, dim3((unsigned)((f.OW + 255) / 256), (unsigned)f.OH), dim3(256), 0, s, f.A, Q,
-                       f.o0, f.o1, f.OH, f.OW, 1.0f / ((float)P * (float)Q), f.y, f.ys0, f.ys1);
-  return hipGetLastError();
+  // the last pass transforms only the rows of the mode's window and writes
+  // their real part, scaled, straight into y
+  if (f.OH <= 0 || f.OW <= 0) return hipSuccess;
+  RowIO io{};
+  io.y = f.y;
+  io.ys0 = f.ys0;
+  io.ys1 = f.ys1;
+  io.OH = f.OH;
+  io.OW = f.OW;
+  io.o0 = f.o0;
+  io.o1 = f.o1;
+  io.scale = 1.0f / ((float)P * (float)Q);
+  return rows_t<true, false, true>(f.A, f.OH, Q, f.twQ, io, s);
 }
 
 }  // namespace ttc
