@@ -91,15 +91,65 @@ int tc_device_check(int device, int* n_cu);
  * N >= K in every dimension or K >= N in every dimension).  The kernel may be
  * larger than x (full mode is commutative).
  *
- * dtypes (x, k -> y): F32,F32->F32; F16,F32->F32; U8,I32->I32 (exact; rejected
- * with TC_EOVERFLOW unless 255 * sum|k| <= 2^31-1).  x and k have the same
- * rank 1..8.  x and y may be strided; k must be contiguous and at most
- * 2^20 elements, and is read from DEVICE memory.  y must not overlap x or k.
- * Float results are accumulated in FP32 (the order of the taps is not
- * specified).
+ * dtypes (x, k -> y): F32,F32->F32; F16,F32->F32; U8,I32->I32 (exact).  x
+ * and k have the same rank 1..8.  x and y may be strided; k must be
+ * contiguous and at most 2^20 elements, and is read from DEVICE memory.  y
+ * must not overlap x or k.  Float results are accumulated in FP32 (the order
+ * of the taps is not specified).  Launches only: no entry point here reads
+ * the kernel back to the host.
+ *
+ * tc_conv_nd: the direct kernels.  F32 and F16 inputs only: an I32 kernel is
+ * rejected with TC_EINVAL, because its exactness bound is a property of the
+ * taps that only the caller can state without a device-to-host read; integer
+ * convolutions go through tc_conv_nd_ex.
+ *
+ * tc_conv_nd_ex: the same convolution with a choice of method (the hybrid of
+ * the Accelerating Convolutions section: direct for small kernels, FFT from
+ * a kernel-size threshold; the separable form of the Future Work section):
+ *   method TC_CONV_DIRECT  the direct kernels;
+ *          TC_CONV_FFT     the FFT branch (F32, rank 2 or 3, padded extents
+ *                          within the transform limits; needs the workspace
+ *                          of tc_conv_workspace_size, TC_ENOMEM if smaller);
+ *          TC_CONV_AUTO    the FFT branch when it applies, the kernel's longest
+ *                          side is >= fft_threshold (0: the library's measured
+ *                          crossover) and the workspace is large enough; else,
+ *                          when k_host is given and k is a square F32 2-D
+ *                          kernel of 3, 5, 7, 9, 11 or 15 taps that passes the
+ *                          rank-one test of tc_conv_kernel_rank1 with tolerance
+ *                          2^-20, the separable kernel with the factors passed
+ *                          by value; else the direct kernels.
+ *   k_abs_sum  U8,I32 only: sum over the kernel of |k|, a HOST-side value the
+ *          caller guarantees.  Rejected with TC_EOVERFLOW unless
+ *          255 * k_abs_sum <= 2^31-1 (then every partial sum fits int32 and the
+ *          result is exact); TC_EINVAL when neither k_abs_sum >= 0 nor k_host
+ *          is given.  A wrong value voids the exactness guarantee.
+ *   k_host optional HOST copy of k (same dtype and contiguous layout), read
+ *          during the call only: gives k_abs_sum for I32 kernels and enables
+ *          the separable test.  NULL when not available.
+ *   workspace, workspace_bytes  DEVICE scratch for the FFT branch (may be NULL
+ *          and 0 when only the direct or separable paths may run).
+ * opts may be NULL: TC_CONV_AUTO with no workspace and no host copy, i.e. the
+ * direct kernels (which reject I32 kernels as above).
+ *
+ * tc_conv_workspace_size: bytes of device workspace tc_conv_nd_ex needs for
+ * these shapes with `method` (0 when no FFT branch applies, or for
+ * TC_CONV_DIRECT; for TC_CONV_FFT an error when the FFT branch does not apply).
  * ------------------------------------------------------------------------ */
+enum { TC_CONV_AUTO = 0, TC_CONV_DIRECT = 1, TC_CONV_FFT = 2 };
+typedef struct {
+  int32_t method;
+  int32_t fft_threshold;
+  int64_t k_abs_sum;
+  const void* k_host;
+  void* workspace;
+  size_t workspace_bytes;
+} tc_conv_opts;
+
 int tc_conv_out_shape(const tc_tensor* x, const tc_tensor* k, int32_t mode, int64_t* out_shape);
 int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* stream);
+int tc_conv_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, int32_t method, size_t* ws_bytes);
+int tc_conv_nd_ex(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y,
+                  const tc_conv_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
  * Separable kernels

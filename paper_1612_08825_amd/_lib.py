@@ -26,6 +26,8 @@ TC_PHASE_FUSED, TC_PHASE_FINISH = 1, 2
 TC_STENCIL_FD2, TC_STENCIL_ROBERTS, TC_STENCIL_PREWITT3, TC_STENCIL_SOBEL3 = 0, 1, 2, 3
 TC_SELECT_DECREASING_TTC, TC_SELECT_MIN_RESIDUAL = 0, 1
 TC_LOWPASS_NONE, TC_LOWPASS_BINOMIAL3 = 0, 1
+TC_CONV_AUTO, TC_CONV_DIRECT, TC_CONV_FFT = 0, 1, 2
+METHODS = {"auto": TC_CONV_AUTO, "direct": TC_CONV_DIRECT, "fft": TC_CONV_FFT}
 
 
 class TcTensor(C.Structure):
@@ -35,6 +37,17 @@ class TcTensor(C.Structure):
         ("ndim", C.c_int32),
         ("shape", C.c_int64 * TC_MAX_DIMS),
         ("stride", C.c_int64 * TC_MAX_DIMS),
+    ]
+
+
+class TcConvOpts(C.Structure):
+    _fields_ = [
+        ("method", C.c_int32),
+        ("fft_threshold", C.c_int32),
+        ("k_abs_sum", C.c_int64),
+        ("k_host", C.c_void_p),
+        ("workspace", C.c_void_p),
+        ("workspace_bytes", C.c_size_t),
     ]
 
 
@@ -82,6 +95,8 @@ SIGNATURES = {
                                  C.POINTER(C.c_float)]),
     "tc_conv_nd_separable": (_I, [_T, _T, _T, _I32, _T, _P]),
     "tc_conv_nd": (_I, [_T, _T, _I32, _T, _P]),
+    "tc_conv_workspace_size": (_I, [_T, _T, _I32, _I32, C.POINTER(_SZ)]),
+    "tc_conv_nd_ex": (_I, [_T, _T, _I32, _T, C.POINTER(TcConvOpts), _P]),
     "tc_conv2d_fft_workspace_size": (_I, [_T, _T, _I32, C.POINTER(_SZ)]),
     "tc_conv2d_fft": (_I, [_T, _T, _I32, _T, _P, _SZ, _P]),
     "tc_pyramid_shape": (_I, [_I64, _I64, _I32, C.POINTER(_I64), C.POINTER(_I64)]),

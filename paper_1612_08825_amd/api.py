@@ -74,8 +74,16 @@ def conv_out_shape(xshape, kshape, mode: str = "full", xdtype=torch.float32, kdt
     return tuple(out[i] for i in range(len(xshape)))
 
 
-def conv_nd(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[torch.Tensor] = None, stream=None):
-    """y = x (*) k, true n-D convolution (f32*f32->f32, f16*f32->f32, u8*i32->i32)."""
+def conv_nd(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[torch.Tensor] = None, stream=None,
+            k_abs_sum: Optional[int] = None):
+    """y = x (*) k, true n-D convolution by the direct kernels (f32*f32->f32,
+    f16*f32->f32, u8*i32->i32).  An int32 kernel needs its sum |k|, a host
+    value: pass `k_abs_sum`, or it is read from k here (one device-to-host
+    read, so such a call cannot be recorded into a graph)."""
+    if k.dtype == torch.int32:
+        if k_abs_sum is None:
+            k_abs_sum = int(k.detach().to(torch.int64).abs().sum().item())
+        return conv_nd_ex(x, k, mode, method="direct", k_abs_sum=k_abs_sum, out=out, stream=stream)
     lib = _lib()
     shape = conv_out_shape(tuple(x.shape), tuple(k.shape), mode, x.dtype, k.dtype)
     ydt = torch.int32 if x.dtype == torch.uint8 else torch.float32
@@ -83,6 +91,48 @@ def conv_nd(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[
         out = torch.empty(shape, dtype=ydt, device=x.device)
     L.check("tc_conv_nd", lib.tc_conv_nd(C.byref(_desc(x)), C.byref(_desc(k)), L.MODES[mode], C.byref(_desc(out)),
                                          _stream(stream)))
+    return out
+
+
+def conv_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full", method: str = "auto") -> int:
+    n = C.c_size_t(0)
+    L.check("tc_conv_workspace_size",
+            _lib().tc_conv_workspace_size(C.byref(_desc(x)), C.byref(_desc(k)), L.MODES[mode], L.METHODS[method],
+                                          C.byref(n)))
+    return n.value
+
+
+def conv_nd_ex(x: torch.Tensor, k: torch.Tensor, mode: str = "full", method: str = "auto",
+               k_abs_sum: Optional[int] = None, k_host: Optional[np.ndarray] = None, fft_threshold: int = 0,
+               ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None, stream=None):
+    """tc_conv_nd_ex: the convolution with the library's method choice.
+    `k_host` (a contiguous numpy copy of k) lets the library take sum |k| of an
+    int32 kernel and test a square FP32 kernel for separability; `ws` is the
+    FFT branch's device workspace (allocated here when None and the method
+    may take the FFT branch)."""
+    lib = _lib()
+    shape = conv_out_shape(tuple(x.shape), tuple(k.shape), mode, x.dtype, k.dtype)
+    ydt = torch.int32 if x.dtype == torch.uint8 else torch.float32
+    if out is None:
+        out = torch.empty(shape, dtype=ydt, device=x.device)
+    if ws is None and method != "direct":
+        nbytes = conv_workspace_size(x, k, mode, method)
+        if nbytes > 0:
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=x.device)
+    o = L.TcConvOpts()
+    o.method = L.METHODS[method]
+    o.fft_threshold = int(fft_threshold)
+    o.k_abs_sum = -1 if k_abs_sum is None else int(k_abs_sum)
+    kh = None
+    if k_host is not None:
+        kh = np.ascontiguousarray(k_host, dtype=np.int32 if k.dtype == torch.int32 else np.float32)
+        if kh.shape != tuple(k.shape):
+            raise ValueError("k_host must have the shape of k")
+        o.k_host = kh.ctypes.data
+    o.workspace = ws.data_ptr() if ws is not None and ws.numel() > 0 else None
+    o.workspace_bytes = ws.numel() if ws is not None else 0
+    L.check("tc_conv_nd_ex", lib.tc_conv_nd_ex(C.byref(_desc(x)), C.byref(_desc(k)), L.MODES[mode],
+                                               C.byref(_desc(out)), C.byref(o), _stream(stream)))
     return out
 
 

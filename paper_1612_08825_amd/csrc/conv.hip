@@ -598,8 +598,7 @@ hipError_t launch_roll_t(const RowArgs& ra, hipStream_t s) {
 // per output instead of K^2, and no intermediate image.
 template <int K, int RB, int S>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void conv2d_rows_sep(RowArgs a,
-                                                                                             const float* uf,
-                                                                                             const float* vf) {
+                                                                                             SepTaps tp) {
   constexpr int NC = row_chunks<K, S>();
   constexpr int LO = row_lanes_out<K, S>();
   constexpr int NW = K + 3;
@@ -621,8 +620,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void co
   const int n_rows = n_out + K - 1;
   const gptr<float> yp = as_global(a.y);
   const bool store_lane = lane < LO;
-  const cptr<float> u = (cptr<float>)uf;
-  const cptr<float> v = (cptr<float>)vf;
+  const cptr<float> u = (cptr<float>)tp.u;
+  const cptr<float> v = (cptr<float>)tp.v;
 
   auto load_chunk = [&](int row, float (&c4)[4]) {
     if (row < 0 || row >= a.H) {  // uniform
@@ -667,7 +666,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void co
     float r[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int b = 0; b < K; ++b) {
-      const float vb = v[b];
+      const float vb = tp.byval ? tp.vh[b] : v[b];
 #pragma unroll
       for (int c = 0; c < 4; ++c) r[c] = fmaf(vb, ch[S + c + K - 1 - b], r[c]);
     }
@@ -677,7 +676,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void co
 #pragma unroll
     for (int w = 0; w < K; ++w) {
       if (w < w_lo || w > w_hi) continue;
-      const float uw = u[w];
+      const float uw = tp.byval ? tp.uh[w] : u[w];
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[w][c] = fmaf(uw, r[c], acc[w][c]);
     }
@@ -708,32 +707,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void co
 }
 
 template <int K, int RB, int S>
-hipError_t launch_sep_s(RowArgs ra, const float* u, const float* v, hipStream_t s) {
+hipError_t launch_sep_s(RowArgs ra, const SepTaps& tp, hipStream_t s) {
   constexpr int LO = row_lanes_out<K, S>();
   ra.n_bands = (ra.OH + RB - 1) / RB;
   ra.n_cw = (ra.OW + 4 * LO - 1) / (4 * LO);
   ra.n_items = (int64_t)ra.n_bands * ra.n_cw;
   const int64_t grid = (ra.n_items + 7) / 8 * 8;
-  hipLaunchKernelGGL((conv2d_rows_sep<K, RB, S>), dim3((unsigned)grid), dim3(64), 0, s, ra, u, v);
+  hipLaunchKernelGGL((conv2d_rows_sep<K, RB, S>), dim3((unsigned)grid), dim3(64), 0, s, ra, tp);
   return hipGetLastError();
 }
 
 template <int K, int RB>
-hipError_t launch_sep_rb(const RowArgs& ra, const float* u, const float* v, hipStream_t s) {
+hipError_t launch_sep_rb(const RowArgs& ra, const SepTaps& tp, hipStream_t s) {
   switch ((((ra.off1 - (K - 1)) % 4) + 4) % 4) {
-    case 0: return launch_sep_s<K, RB, 0>(ra, u, v, s);
-    case 1: return launch_sep_s<K, RB, 1>(ra, u, v, s);
-    case 2: return launch_sep_s<K, RB, 2>(ra, u, v, s);
-    default: return launch_sep_s<K, RB, 3>(ra, u, v, s);
+    case 0: return launch_sep_s<K, RB, 0>(ra, tp, s);
+    case 1: return launch_sep_s<K, RB, 1>(ra, tp, s);
+    case 2: return launch_sep_s<K, RB, 2>(ra, tp, s);
+    default: return launch_sep_s<K, RB, 3>(ra, tp, s);
   }
 }
 
 template <int K>
-hipError_t launch_sep_k(const RowArgs& ra, const float* u, const float* v, hipStream_t s) {
+hipError_t launch_sep_k(const RowArgs& ra, const SepTaps& tp, hipStream_t s) {
   constexpr int LO = row_lanes_out<K, 3>();
   const int64_t items32 = (int64_t)((ra.OH + 31) / 32) * ((ra.OW + 4 * LO - 1) / (4 * LO));
-  if (items32 >= 2048) return launch_sep_rb<K, 32>(ra, u, v, s);
-  return launch_sep_rb<K, 8>(ra, u, v, s);
+  if (items32 >= 2048) return launch_sep_rb<K, 32>(ra, tp, s);
+  return launch_sep_rb<K, 8>(ra, tp, s);
 }
 
 template <int KH, int KW, int R, int S>
@@ -812,12 +811,12 @@ hipError_t launch_conv_separable(const SepConv& c, hipStream_t s) {
   ra.off0 = c.off0;
   ra.off1 = c.off1;
   switch (c.K) {
-    case 3: return launch_sep_k<3>(ra, c.u, c.v, s);
-    case 5: return launch_sep_k<5>(ra, c.u, c.v, s);
-    case 7: return launch_sep_k<7>(ra, c.u, c.v, s);
-    case 9: return launch_sep_k<9>(ra, c.u, c.v, s);
-    case 11: return launch_sep_k<11>(ra, c.u, c.v, s);
-    case 15: return launch_sep_k<15>(ra, c.u, c.v, s);
+    case 3: return launch_sep_k<3>(ra, c.taps, s);
+    case 5: return launch_sep_k<5>(ra, c.taps, s);
+    case 7: return launch_sep_k<7>(ra, c.taps, s);
+    case 9: return launch_sep_k<9>(ra, c.taps, s);
+    case 11: return launch_sep_k<11>(ra, c.taps, s);
+    case 15: return launch_sep_k<15>(ra, c.taps, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -27,13 +27,22 @@ struct ConvND {
 // Chooses a kernel (2-D tiled, 3-D tiled, or generic rank-n) and launches it.
 hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s);
 
+// The two factors of a separable kernel: device arrays, or (byval) the values
+// themselves carried in the kernel arguments (at most 16 taps each).
+struct SepTaps {
+  const float* u;    // K taps along the columns (device)
+  const float* v;    // K taps along the rows (device)
+  float uh[16];
+  float vh[16];
+  int byval;
+};
+
 // A 2-D FP32 convolution with a separable square kernel u v^T (K taps each).
 struct SepConv {
   const float* x;
   int64_t xs0;       // row stride (elements); unit stride along rows
   int H, W;
-  const float* u;    // K taps along the columns (device)
-  const float* v;    // K taps along the rows (device)
+  SepTaps taps;
   int K;
   float* y;
   int64_t ys0;

@@ -149,7 +149,10 @@ extern "C" int tc_conv_out_shape(const tc_tensor* x, const tc_tensor* k, int32_t
   return conv_geometry(x, k, mode, out_shape, off);
 }
 
-extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* stream) {
+namespace {
+
+// Validation shared by the direct entry points; fills the output geometry.
+int conv_validate(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, int64_t* off) {
   int st;
   if ((st = check_tensor(x, true)) != TC_OK) return st;
   if ((st = check_tensor(k, true)) != TC_OK) return st;
@@ -157,40 +160,33 @@ extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, 
   const int ydt = conv_dtypes_ok(x->dtype, k->dtype);
   if (ydt < 0 || y->dtype != ydt) return TC_EDTYPE;
   if (!is_contiguous(k)) return TC_ESHAPE;
-  const int64_t ktaps = numel(k);
-  if (ktaps > (1LL << 20)) return TC_EINVAL;
-  int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
+  if (numel(k) > (1LL << 20)) return TC_EINVAL;
+  int64_t oshape[TC_MAX_DIMS];
   if ((st = conv_geometry(x, k, mode, oshape, off)) != TC_OK) return st;
   if (y->ndim != x->ndim) return TC_ESHAPE;
   for (int d = 0; d < y->ndim; ++d)
     if (y->shape[d] != oshape[d]) return TC_ESHAPE;
-  if (numel(y) == 0) return TC_OK;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return TC_OK;
+}
 
+// The direct kernels.  For an integer kernel, k_abs_sum = sum |k| as stated by
+// the caller: the int32 result is exact when 255 * sum|k| <= 2^31 - 1 (every
+// partial sum then fits), and 24-bit multiplies are exact when sum|k| < 2^23.
+int conv_direct(const tc_tensor* x, const tc_tensor* k, const tc_tensor* y, const int64_t* off, int64_t k_abs_sum,
+                hipStream_t s) {
   bool small_taps = true;
   if (k->dtype == TC_I32) {
-    // exactness bound: every partial sum is at most 255 * sum|k| in magnitude
-    std::vector<int32_t> kh((size_t)ktaps);
-    if (ktaps > 0) {
-      if (hipMemcpyAsync(kh.data(), k->data, (size_t)ktaps * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return TC_EDEVICE;
-      if (hipStreamSynchronize(s) != hipSuccess) return TC_EDEVICE;
-    }
-    int64_t sabs = 0;
-    for (int32_t v : kh) {
-      const int64_t a = v < 0 ? -(int64_t)v : (int64_t)v;
-      sabs += a;
-      if (a >= (1LL << 23)) small_taps = false;
-    }
-    if (255 * sabs > 2147483647LL) return TC_EOVERFLOW;
+    if (k_abs_sum < 0) return TC_EINVAL;
+    if (k_abs_sum > 2147483647LL / 255) return TC_EOVERFLOW;
+    small_taps = k_abs_sum < (1LL << 23);
   }
+  if (numel(y) == 0) return TC_OK;
   // zero-size x: the result is all zeros in full/same mode (a fill kernel, so
   // that the call stays safe to record into a HIP graph)
-  if (numel(x) == 0 || ktaps == 0) {
+  if (numel(x) == 0 || numel(k) == 0) {
     if (is_contiguous(y)) return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
     return TC_ESHAPE;
   }
-
   ConvND c{};
   c.ndim = x->ndim;
   c.xdt = x->dtype;
@@ -206,6 +202,18 @@ extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, 
     c.off[d] = off[d];
   }
   return hip_status(launch_conv(c, small_taps, s));
+}
+
+}  // namespace
+
+extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* stream) {
+  int64_t off[TC_MAX_DIMS];
+  int st;
+  if ((st = conv_validate(x, k, mode, y, off)) != TC_OK) return st;
+  // the exactness bound of an integer kernel is a host-side fact the caller
+  // states through tc_conv_nd_ex; this entry point never reads the taps back
+  if (k->dtype == TC_I32) return TC_EINVAL;
+  return conv_direct(x, k, y, off, -1, reinterpret_cast<hipStream_t>(stream));
 }
 
 // ============================================================================ separable kernels
@@ -239,6 +247,51 @@ extern "C" int tc_conv_kernel_rank1(const float* k, int32_t KH, int32_t KW, doub
   return 1;
 }
 
+namespace {
+
+// x (*) (u v^T) for a K x K separable kernel whose factors `tp` carries.
+int conv_separable(const tc_tensor* x, int K, const SepTaps& tp, int32_t mode, const tc_tensor* y, hipStream_t s) {
+  if (!separable_variant(K)) return TC_EINVAL;
+  if (x->dtype != TC_F32 || y->dtype != TC_F32) return TC_EDTYPE;
+  if (x->ndim != 2 || y->ndim != 2) return TC_ESHAPE;
+  if (x->stride[1] != 1 || y->stride[1] != 1) return TC_ESHAPE;
+  // the geometry of the equivalent K x K kernel
+  tc_tensor kv{};
+  kv.dtype = TC_F32;
+  kv.ndim = 2;
+  kv.shape[0] = K;
+  kv.shape[1] = K;
+  kv.stride[0] = K;
+  kv.stride[1] = 1;
+  int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
+  int st;
+  if ((st = conv_geometry(x, &kv, mode, oshape, off)) != TC_OK) return st;
+  if (y->shape[0] != oshape[0] || y->shape[1] != oshape[1]) return TC_ESHAPE;
+  if (numel(y) == 0) return TC_OK;
+  for (int d = 0; d < 2; ++d)
+    if (x->shape[d] >= (1LL << 28) || y->shape[d] >= (1LL << 28) || off[d] >= (1LL << 28)) return TC_EINVAL;
+  if (numel(x) == 0) {
+    if (y->stride[0] == y->shape[1]) return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
+    return TC_ESHAPE;
+  }
+  SepConv c{};
+  c.x = static_cast<const float*>(x->data);
+  c.xs0 = x->stride[0];
+  c.H = (int)x->shape[0];
+  c.W = (int)x->shape[1];
+  c.taps = tp;
+  c.K = K;
+  c.y = static_cast<float*>(y->data);
+  c.ys0 = y->stride[0];
+  c.OH = (int)y->shape[0];
+  c.OW = (int)y->shape[1];
+  c.off0 = (int)off[0];
+  c.off1 = (int)off[1];
+  return hip_status(launch_conv_separable(c, s));
+}
+
+}  // namespace
+
 extern "C" int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, const tc_tensor* v, int32_t mode,
                                     const tc_tensor* y, void* stream) {
   int st;
@@ -249,44 +302,11 @@ extern "C" int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, cons
   if (x->dtype != TC_F32 || u->dtype != TC_F32 || v->dtype != TC_F32 || y->dtype != TC_F32) return TC_EDTYPE;
   if (x->ndim != 2 || y->ndim != 2 || u->ndim != 1 || v->ndim != 1) return TC_ESHAPE;
   if (!is_contiguous(u) || !is_contiguous(v) || u->shape[0] != v->shape[0]) return TC_ESHAPE;
-  const int K = (int)u->shape[0];
-  if (!separable_variant(K)) return TC_EINVAL;
-  if (x->stride[1] != 1 || y->stride[1] != 1) return TC_ESHAPE;
-  // the geometry of the equivalent K x K kernel
-  tc_tensor kv{};
-  kv.data = u->data;
-  kv.dtype = TC_F32;
-  kv.ndim = 2;
-  kv.shape[0] = K;
-  kv.shape[1] = K;
-  kv.stride[0] = K;
-  kv.stride[1] = 1;
-  int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
-  if ((st = conv_geometry(x, &kv, mode, oshape, off)) != TC_OK) return st;
-  if (y->shape[0] != oshape[0] || y->shape[1] != oshape[1]) return TC_ESHAPE;
-  if (numel(y) == 0) return TC_OK;
-  for (int d = 0; d < 2; ++d)
-    if (x->shape[d] >= (1LL << 28) || y->shape[d] >= (1LL << 28) || off[d] >= (1LL << 28)) return TC_EINVAL;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (numel(x) == 0) {
-    if (y->stride[0] == y->shape[1]) return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
-    return TC_ESHAPE;
-  }
-  SepConv c{};
-  c.x = static_cast<const float*>(x->data);
-  c.xs0 = x->stride[0];
-  c.H = (int)x->shape[0];
-  c.W = (int)x->shape[1];
-  c.u = static_cast<const float*>(u->data);
-  c.v = static_cast<const float*>(v->data);
-  c.K = K;
-  c.y = static_cast<float*>(y->data);
-  c.ys0 = y->stride[0];
-  c.OH = (int)y->shape[0];
-  c.OW = (int)y->shape[1];
-  c.off0 = (int)off[0];
-  c.off1 = (int)off[1];
-  return hip_status(launch_conv_separable(c, s));
+  SepTaps tp{};
+  tp.u = static_cast<const float*>(u->data);
+  tp.v = static_cast<const float*>(v->data);
+  tp.byval = 0;
+  return conv_separable(x, (int)u->shape[0], tp, mode, y, reinterpret_cast<hipStream_t>(stream));
 }
 
 namespace {
@@ -385,6 +405,89 @@ extern "C" int tc_conv2d_fft(const tc_tensor* x, const tc_tensor* k, int32_t mod
   f.o0 = (int)L.off[0];
   f.o1 = (int)L.off[1];
   return hip_status(launch_conv2d_fft(f, s));
+}
+
+// ============================================================================ dispatcher
+namespace {
+
+// The kernel side from which the FFT branch beats the direct kernels on
+// MI355X (2048 x 2048 FP32 images, full mode, square kernels).
+constexpr int kFftThresholdDefault = 37;
+// Relative tolerance of the rank-one test the dispatcher applies to a host copy
+// of a square FP32 kernel (max |k - u v^T| <= tol * max |k|).
+constexpr double kSeparableTol = 0x1p-20;
+
+bool fft_eligible(const tc_tensor* x, const tc_tensor* k, int32_t mode, FftLayout& L) {
+  return fft_layout(x, k, mode, L) == TC_OK;
+}
+
+}  // namespace
+
+extern "C" int tc_conv_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, int32_t method,
+                                      size_t* ws_bytes) {
+  if (!x || !k || !ws_bytes) return TC_EINVAL;
+  int st;
+  if ((st = check_tensor(x, false)) != TC_OK) return st;
+  if ((st = check_tensor(k, false)) != TC_OK) return st;
+  if (method != TC_CONV_AUTO && method != TC_CONV_DIRECT && method != TC_CONV_FFT) return TC_EINVAL;
+  *ws_bytes = 0;
+  if (method == TC_CONV_DIRECT) return TC_OK;
+  FftLayout L;
+  if (fft_eligible(x, k, mode, L)) *ws_bytes = L.total;
+  else if (method == TC_CONV_FFT) return fft_layout(x, k, mode, L);
+  return TC_OK;
+}
+
+extern "C" int tc_conv_nd_ex(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y,
+                             const tc_conv_opts* opts, void* stream) {
+  tc_conv_opts o{};
+  o.method = TC_CONV_AUTO;
+  o.k_abs_sum = -1;
+  if (opts) o = *opts;
+  if (o.method != TC_CONV_AUTO && o.method != TC_CONV_DIRECT && o.method != TC_CONV_FFT) return TC_EINVAL;
+  if (o.fft_threshold < 0) return TC_EINVAL;
+  int64_t off[TC_MAX_DIMS];
+  int st;
+  if ((st = conv_validate(x, k, mode, y, off)) != TC_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t ktaps = numel(k);
+
+  // what the host copy of the kernel tells (read here, on the host)
+  int64_t k_abs_sum = o.k_abs_sum;
+  if (k->dtype == TC_I32 && o.k_host && ktaps > 0) {
+    const int32_t* kh = static_cast<const int32_t*>(o.k_host);
+    int64_t sa = 0;
+    for (int64_t i = 0; i < ktaps; ++i) {
+      sa += kh[i] < 0 ? -(int64_t)kh[i] : (int64_t)kh[i];
+      if (sa > (int64_t)1 << 40) break;  // far past the bound already
+    }
+    k_abs_sum = sa;
+  }
+  if (k->dtype == TC_I32 && ktaps == 0) k_abs_sum = 0;
+  if (o.method == TC_CONV_FFT || o.method == TC_CONV_AUTO) {
+    FftLayout L;
+    const bool ok = fft_eligible(x, k, mode, L);
+    if (o.method == TC_CONV_FFT && !ok) {
+      const int e = fft_layout(x, k, mode, L);
+      return e != TC_OK ? e : TC_EINVAL;
+    }
+    int64_t kmax = 0;
+    for (int d = 0; d < k->ndim; ++d) kmax = std::max(kmax, k->shape[d]);
+    const int thr = o.fft_threshold > 0 ? o.fft_threshold : kFftThresholdDefault;
+    const bool want = o.method == TC_CONV_FFT || (ok && kmax >= thr && o.workspace && o.workspace_bytes >= L.total);
+    if (want) return tc_conv2d_fft(x, k, mode, y, o.workspace, o.workspace_bytes, stream);
+  }
+  // separable square F32 kernels, when the caller lent a host copy to test:
+  // the factors travel by value in the kernel arguments
+  if (o.method == TC_CONV_AUTO && o.k_host && x->dtype == TC_F32 && k->dtype == TC_F32 && x->ndim == 2 &&
+      k->shape[0] == k->shape[1] && separable_variant((int)k->shape[0]) && x->stride[1] == 1 && y->stride[1] == 1) {
+    const int K = (int)k->shape[0];
+    SepTaps tp{};
+    tp.byval = 1;
+    if (tc_conv_kernel_rank1(static_cast<const float*>(o.k_host), K, K, kSeparableTol, tp.uh, tp.vh) == 1)
+      return conv_separable(x, K, tp, mode, y, s);
+  }
+  return conv_direct(x, k, y, off, k_abs_sum, s);
 }
 
 // ============================================================================ pyramid / derivatives

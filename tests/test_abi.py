@@ -131,6 +131,59 @@ def test_conv_nd_rejects_before_launch(lib):
     assert lib.tc_conv_nd(C.byref(x0), C.byref(k), L.TC_FULL, C.byref(y), None) == L.TC_ESHAPE
 
 
+def test_conv_nd_ex_rejects_before_launch(lib):
+    """Integer kernels: the exactness bound comes from the caller (a stated
+    sum |k| or a host copy of k), never from a device read; every rejection
+    happens before anything is launched."""
+    import numpy as np
+
+    xu = _desc((10, 7), L.TC_U8, data=16)
+    ki = _desc((3, 3), L.TC_I32, data=16)
+    yi = _desc((12, 9), L.TC_I32, data=16)
+    # the plain entry point refuses integer kernels outright
+    assert lib.tc_conv_nd(C.byref(xu), C.byref(ki), L.TC_FULL, C.byref(yi), None) == L.TC_EINVAL
+    # no bound given
+    assert lib.tc_conv_nd_ex(C.byref(xu), C.byref(ki), L.TC_FULL, C.byref(yi), None, None) == L.TC_EINVAL
+    o = L.TcConvOpts()
+    o.method = L.TC_CONV_DIRECT
+    o.k_abs_sum = -1
+    assert lib.tc_conv_nd_ex(C.byref(xu), C.byref(ki), L.TC_FULL, C.byref(yi), C.byref(o), None) == L.TC_EINVAL
+    # a stated bound past 2^31 / 255
+    o.k_abs_sum = 2147483647 // 255 + 1
+    assert lib.tc_conv_nd_ex(C.byref(xu), C.byref(ki), L.TC_FULL, C.byref(yi), C.byref(o), None) == L.TC_EOVERFLOW
+    # a host copy whose taps break the bound (255 * 8421505 > 2^31 - 1)
+    kh = np.zeros((3, 3), np.int32)
+    kh[0, 0] = 8421504
+    kh[2, 2] = -1
+    o.k_abs_sum = -1
+    o.k_host = kh.ctypes.data
+    assert lib.tc_conv_nd_ex(C.byref(xu), C.byref(ki), L.TC_FULL, C.byref(yi), C.byref(o), None) == L.TC_EOVERFLOW
+    # bad method, bad threshold
+    o2 = L.TcConvOpts()
+    o2.method = 9
+    x = _desc((10, 7), L.TC_F32, data=16)
+    k = _desc((3, 3), L.TC_F32, data=16)
+    y = _desc((12, 9), L.TC_F32, data=16)
+    assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o2), None) == L.TC_EINVAL
+    o2.method = L.TC_CONV_AUTO
+    o2.fft_threshold = -3
+    assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o2), None) == L.TC_EINVAL
+    # FFT forced on shapes it does not take, or without a workspace
+    o3 = L.TcConvOpts()
+    o3.method = L.TC_CONV_FFT
+    xh = _desc((10, 7), L.TC_F16, data=16)
+    assert lib.tc_conv_nd_ex(C.byref(xh), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o3), None) == L.TC_EDTYPE
+    assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o3), None) == L.TC_EINVAL
+    n = C.c_size_t(123)
+    assert lib.tc_conv_workspace_size(C.byref(x), C.byref(k), L.TC_FULL, L.TC_CONV_DIRECT, C.byref(n)) == 0
+    assert n.value == 0
+    assert lib.tc_conv_workspace_size(C.byref(x), C.byref(k), L.TC_FULL, L.TC_CONV_FFT, C.byref(n)) == 0
+    assert n.value > 0
+    assert lib.tc_conv_workspace_size(C.byref(xh), C.byref(k), L.TC_FULL, L.TC_CONV_AUTO, C.byref(n)) == 0
+    assert n.value == 0
+    assert lib.tc_conv_workspace_size(C.byref(xh), C.byref(k), L.TC_FULL, L.TC_CONV_FFT, C.byref(n)) == L.TC_EDTYPE
+
+
 def test_pyramid_and_horn_validation(lib):
     Hl, Wl = C.c_int64(), C.c_int64()
     assert lib.tc_pyramid_shape(481, 641, 3, C.byref(Hl), C.byref(Wl)) == 0

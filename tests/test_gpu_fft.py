@@ -12,7 +12,12 @@ one complex product per point and transforms back; with ||x (*) k||_2 <=
     ||y - y64||_2 <= TAU_FFT ||x||_2 ||k||_1,   TAU_FFT = 3 * 8u * log2(PQ) + 4u,
 
 which the tests check, together with the element-wise consequence
-max |y - y64| <= ||y - y64||_2."""
+max |y - y64| <= ||y - y64||_2.  That bound is a worst case and sits two to
+three orders of magnitude above the measured errors, so on its own it would
+let through a transform with a wrong twiddle in a late stage; the tests also
+hold the measured error to RATIO_MAX of the bound and to REL2_MAX relative to
+||y64||_2 (rounding errors of an FFT grow like sqrt(log2 N) u on random data).
+"""
 import math
 
 import numpy as np
@@ -24,6 +29,9 @@ import oracle as O
 pytestmark = pytest.mark.gpu
 
 U = 2.0 ** -24
+RATIO_MAX = 0.05
+TAU_CONV_ABS = 1e-5
+REL2_MAX = 1e-5
 
 
 def tau_fft(xs, ks):
@@ -47,7 +55,10 @@ def check(x, k, y, ref):
     err = np.asarray(y, dtype=np.float64) - ref
     bound = tau_fft(x.shape, k.shape) * np.linalg.norm(x) * np.abs(k).sum()
     e2 = float(np.linalg.norm(err))
-    assert e2 <= bound, (e2, bound)
+    assert e2 <= RATIO_MAX * bound, (e2, bound)
+    n2 = float(np.linalg.norm(ref))
+    if n2 > 0:
+        assert e2 <= REL2_MAX * n2, (e2, n2)
     return e2 / bound
 
 
@@ -83,12 +94,17 @@ def test_fft_large_against_direct_and_sampled_oracle(api):
     torch.cuda.synchronize()
     bound = tau_fft(x.shape, k.shape) * np.linalg.norm(x) * np.abs(k).sum()
     diff = (yf.double() - yd.double()).cpu().numpy()
-    assert float(np.linalg.norm(diff)) <= bound
+    assert float(np.linalg.norm(diff)) <= RATIO_MAX * bound
+    assert float(np.linalg.norm(diff)) <= REL2_MAX * float(torch.linalg.vector_norm(yd.double()))
     idx = [(0, 0), (15, 15), (1000, 1234), (2077, 2077), (2060, 5), (30, 2070)]
     want = O.conv_at(x, k, "full", idx)
     got = yf.cpu().numpy()
+    # per element: an FFT output carries about the rms error of the whole
+    # result, i.e. ||err||_2 / sqrt(#outputs); allow 8 times that estimate
+    # (taken from the measured norm-wise error against the direct kernels)
+    rms = float(np.linalg.norm(diff)) / np.sqrt(diff.size)
     for (i, j), w in zip(idx, want):
-        assert abs(float(got[i, j]) - float(w)) <= bound, (i, j)
+        assert abs(float(got[i, j]) - float(w)) <= max(8 * rms, TAU_CONV_ABS * abs(float(w))), (i, j)
 
 
 def test_hybrid_dispatch(api):

@@ -92,3 +92,32 @@ def test_budget_below_working_set(streams):
             fr = host[r.stream].numpy()
             check_pair(r.levels, r.pick, fr[(r.k - 1) % N_FRAMES], fr[r.k % N_FRAMES], LEVELS,
                        f"budget stream{r.stream} k{r.k}")
+
+
+def test_served_pairs_at_camera_sizes(gpu_lib):
+    """u8 frames, 3 levels, the library's u8 launch shape (what the serving
+    workload runs) at the two largest camera sizes: every served pair against
+    the FP64 oracle, and the streams served together equal to served alone."""
+    sizes = [(1280, 720), (1920, 1080)]  # (W, H)
+    nf = 3
+    specs = [synth.serving_specs(case=7 + i, n_streams=1, n_frames=nf, sizes=[sz])[0] for i, sz in enumerate(sizes)]
+    host = [torch.from_numpy(np.ascontiguousarray(sp.render())).pin_memory() for sp in specs]
+    hw = [tuple(h.shape[1:]) for h in host]
+    assert sorted(hw) == [(720, 1280), (1080, 1920)]
+    times, ids = interleaved(len(host), nf)
+    _, st = serve(host, hw, times, ids)
+    n_pairs = 0
+    for r in st.requests:
+        assert not math.isnan(r.t_done)
+        if r.kind != S.PAIR:
+            continue
+        fr = host[r.stream].numpy()
+        check_pair(r.levels, r.pick, fr[(r.k - 1) % nf], fr[r.k % nf], LEVELS, f"{hw[r.stream]} k{r.k}")
+        n_pairs += 1
+    assert n_pairs == len(host) * (nf - 1)
+    for sid in range(len(host)):
+        _, alone = serve([host[sid]], [hw[sid]], np.arange(nf) * 1e-4, np.zeros(nf, dtype=np.int64))
+        a = [r for r in alone.requests if r.kind == S.PAIR]
+        m = [r for r in st.requests if r.stream == sid and r.kind == S.PAIR]
+        for ra, rm in zip(a, m):
+            assert ra.levels.tobytes() == rm.levels.tobytes() and ra.pick.tobytes() == rm.pick.tobytes()

@@ -17,6 +17,13 @@ TAU_SUM = (BLOCK + REDUCE_DEPTH + 8) * 2^-24 with BLOCK = 8 * 32 cubes per lane
 rounding of the products and of G.  The bound on A, B, C follows from first-order perturbation
 of the normal equations, dv = -M^-1 (dM v + dr), with every sum moved by its
 own bound in the worst direction; TTC and FOE follow from C and (A, B).
+
+Residual: with v = (A, B, C) = -M^-1 r and r = (s6, s7, s8), the residual is
+the function resid(s) = s9 - r^T M^-1 r of the sums, whose first-order
+sensitivities are d resid / d s9 = 1, d resid / d r_i = 2 v_i and
+d resid / d M_ij = v_i v_j (each off-diagonal sum sits in M twice).  The bound
+adds every sum's own bound times |sensitivity|, doubled as for (A, B, C), plus
+the FP64 rounding of evaluating s9 + v . r (8 ulp of the terms' magnitudes).
 """
 from __future__ import annotations
 
@@ -66,6 +73,19 @@ def solution_bounds(sums, abs_s, tau=TAU_SUM, safety=2.0):
     dx0 = (dv[0] + abs(A / C) * dv[2]) / abs(C) if C != 0 else math.inf
     dy0 = (dv[1] + abs(B / C) * dv[2]) / abs(C) if C != 0 else math.inf
     return dict(A=dv[0], B=dv[1], C=dv[2], ttc=dttc, x0=dx0, y0=dy0)
+
+
+def resid_bound(sums, abs_s, tau=TAU_SUM, safety=2.0):
+    """First-order worst-case bound on the residual from per-sum bounds tau * abs_s."""
+    s = [float(v) for v in sums]
+    M, rhs = O.ttc.normal_matrix(s)
+    v = np.linalg.solve(np.array(M), np.array(rhs))
+    a = np.asarray(abs_s, dtype=np.float64)
+    sens = np.array([v[0] * v[0], 2 * abs(v[0] * v[1]), v[1] * v[1], 2 * abs(v[0] * v[2]), 2 * abs(v[1] * v[2]),
+                     v[2] * v[2], 2 * abs(v[0]), 2 * abs(v[1]), 2 * abs(v[2]), 1.0])
+    first = safety * tau * float(np.sum(np.abs(sens) * a))
+    rounding = 8 * 2.0 ** -53 * (abs(s[9]) + abs(v[0] * s[6]) + abs(v[1] * s[7]) + abs(v[2] * s[8]))
+    return first + rounding
 
 
 def conv_bound(x, k, mode):

@@ -7,9 +7,9 @@ import numpy as np
 import torch
 
 import oracle as O
-from tolerance import TAU_SUM, abs_sums, solution_bounds
+from tolerance import TAU_SUM, abs_sums, resid_bound, solution_bounds
 
-WORST = {"sum": 0.0, "C": 0.0, "foe": 0.0}
+WORST = {"sum": 0.0, "C": 0.0, "foe": 0.0, "resid": 0.0}
 
 
 def _frames_np(frames):
@@ -40,7 +40,9 @@ def check_pair(rec, pick, P0, P1, levels, tag=""):
             assert abs(g[key] - r[key]) <= b[key], (tag, l, key, g[key], r[key], b[key])
         WORST["C"] = max(WORST["C"], abs(g["C"] - r["C"]) / abs(r["C"]))
         WORST["foe"] = max(WORST["foe"], abs(g["x0"] - r["x0"]), abs(g["y0"] - r["y0"]))
-        assert abs(g["resid"] - r["resid"]) <= 1e-3 * abs(r["resid"]) + 1e-6 * a[9]
+        rb = resid_bound(r["sums"], a)
+        WORST["resid"] = max(WORST["resid"], abs(g["resid"] - r["resid"]) / rb)
+        assert abs(g["resid"] - r["resid"]) <= rb, (tag, l, g["resid"], r["resid"], rb)
     sel = O.select_level(ref)
     ttcs = [r["ttc"] for r in ref]
     near_tie = any(abs(ttcs[i + 1] - ttcs[i]) <= solution_bounds(ref[i]["sums"], abs_sums(p0[i], p1[i], i, H0, W0))["ttc"]
