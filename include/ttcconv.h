@@ -443,6 +443,27 @@ int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_t* ws_bytes
 int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_t levels, void* ws, size_t ws_bytes,
                  tc_ttc_level* levels_out, tc_ttc_pick* pick_out, void* stream);
 
+/* ------------------------------------------------------------------------
+ * tc_ttc_solve without a workspace, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.
+ *
+ * Same arguments (minus ws), results and errors as tc_ttc_solve; the partial
+ * sums go to a scratch array of TC_NOALLOC_SCRATCH_BYTES (4 MiB) held in the
+ * library's device memory, one copy per GPU, kept until the process ends.  A
+ * pair whose workspace (tc_ttc_workspace_size) exceeds that is rejected with
+ * TC_ENOMEM before anything is launched (square frames up to 9984 x 9984
+ * with 4 levels, 19968 x 19968 with one).  The first call on a device looks up the array's address on
+ * the current device (the stream must belong to it); nothing is allocated or
+ * freed, by this call or its kernels.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, or two host threads)
+ * race and must be ordered by the caller.  No part of the array needs to
+ * start at zero (each call writes every partial it reads).  Launches only.
+ * ------------------------------------------------------------------------ */
+#define TC_NOALLOC_SCRATCH_BYTES (4u << 20)
+int tc_ttc_solve_noalloc(const tc_tensor* prev, const tc_tensor* next, int32_t levels, tc_ttc_level* levels_out,
+                         tc_ttc_pick* pick_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,6 +27,7 @@ TC_STENCIL_FD2, TC_STENCIL_ROBERTS, TC_STENCIL_PREWITT3, TC_STENCIL_SOBEL3 = 0, 
 TC_SELECT_DECREASING_TTC, TC_SELECT_MIN_RESIDUAL = 0, 1
 TC_LOWPASS_NONE, TC_LOWPASS_BINOMIAL3 = 0, 1
 TC_CONV_AUTO, TC_CONV_DIRECT, TC_CONV_FFT = 0, 1, 2
+TC_NOALLOC_SCRATCH_BYTES = 4 << 20
 METHODS = {"auto": TC_CONV_AUTO, "direct": TC_CONV_DIRECT, "fft": TC_CONV_FFT}
 
 
@@ -118,6 +119,7 @@ SIGNATURES = {
     "tc_ttc_variant_workspace_size": (_I, [_I64, _I64, _I32, _I32, _I32, C.POINTER(_SZ)]),
     "tc_ttc_solve_variant": (_I, [_T, _T, _I32, _I32, _I32, _P, _SZ, _P, _P, _P]),
     "tc_ttc_solve": (_I, [_T, _T, _I32, _P, _SZ, _P, _P, _P]),
+    "tc_ttc_solve_noalloc": (_I, [_T, _T, _I32, _P, _P, _P]),
 }
 
 _lib = None

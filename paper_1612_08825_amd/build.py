@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libttcconv.so")
 
-SOURCES = ["conv.hip", "fft.hip", "pyramid.hip", "ttc.hip", "ttc_variant.hip", "ttcconv.cpp"]
+SOURCES = ["conv.hip", "fft.hip", "pyramid.hip", "ttc.hip", "ttc_variant.hip", "noalloc.hip", "ttcconv.cpp"]
 
 ARCH = "gfx950"
 COMMON = [
