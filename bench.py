@@ -55,6 +55,7 @@ def parse():
                     help="only the convolution sweep (with --profile: eager launches, no graph, for rocprofv3)")
     ap.add_argument("--save-frames", default=None, help="render the batch, save it to this .npz and exit")
     ap.add_argument("--load-frames", default=None, help="take the batch from a .npz written by --save-frames")
+    ap.add_argument("--tuning", default=None, help="band_rows,groups_per_cu for the fused pass (default: the library's)")
     return ap.parse_args()
 
 
@@ -708,7 +709,8 @@ def main():
         np.savez(args.save_frames, **{f"s{i}": v.cpu().numpy() for i, v in enumerate(vids)})
         print(f"[bench] saved frames to {args.save_frames}", file=sys.stderr, flush=True)
         return
-    plan = api.TTCPlan([api.seq_from_frames(v, LEVELS) for v in vids], torch.float16, keep=vids)
+    tuning = tuple(int(v) for v in args.tuning.split(",")) if args.tuning else None
+    plan = api.TTCPlan([api.seq_from_frames(v, LEVELS) for v in vids], torch.float16, keep=vids, tuning=tuning)
     plan.upload()
     frame_bytes, flops, pair_px = fused_work(specs, LEVELS, 2)
     partial_bytes = plan.ws_bytes
@@ -782,7 +784,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(ach_gb, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(ach_gb / HBM_PEAK_GBPS, 4)}
     roof["traffic"] = profiled_traffic()
-    rh, gpc = api.tuning_default(torch.float16, LEVELS)
+    rh, gpc = tuning if tuning else api.tuning_default(torch.float16, LEVELS)
     roof["kernel"] = f"ttc_fused<_Float16, {LEVELS}, {rh}>"
     roof["launch"] = {"band_rows": rh, "groups_per_cu": gpc}
     roof["kernel_ms"] = round(fused_avg, 4)

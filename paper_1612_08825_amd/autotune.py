@@ -64,14 +64,19 @@ def best(rows: List[Dict]) -> Dict:
 
 
 def workloads(torch):
-    """Representative batches: the batched f16 workload (4 levels) and a u8
-    mix like the serving streams (3 levels)."""
+    """Representative batches: the batched f16 workload and a u8 mix like the
+    serving streams, each swept at every level count (1..4)."""
     from . import synth
 
-    f16 = [s.render(device="cuda") for s in synth.batched_specs()]
-    u8 = [s.render(device="cuda") for s in synth.serving_specs(n_streams=64)]
-    torch.cuda.synchronize()
-    return {("f16", 4): f16, ("u8", 3): u8}
+    f16 = []
+    for s in synth.batched_specs():
+        f16.append(s.render(device="cuda"))
+        torch.cuda.synchronize()  # keep the queue shallow while rendering
+    u8 = []
+    for s in synth.serving_specs(n_streams=64):
+        u8.append(s.render(device="cuda"))
+        torch.cuda.synchronize()
+    return {("f16", lv): f16 for lv in (4, 3, 2, 1)} | {("u8", lv): u8 for lv in (3, 4, 2, 1)}
 
 
 def main():
@@ -83,12 +88,12 @@ def main():
 
     table = {}
     for (dt, levels), vids in workloads(torch).items():
+        print(f"[tune] {dt} {levels} levels", file=sys.stderr, flush=True)
         rows = sweep(vids, levels, reps=args.reps)
         b = best(rows)
         table[f"{dt}/L{levels}"] = {"best": {"band_rows": b["band_rows"], "groups_per_cu": b["groups_per_cu"],
                                              "ms": b["ms"]}, "sweep": rows}
-        del vids
-        torch.cuda.empty_cache()
+    torch.cuda.empty_cache()
     text = json.dumps(table, indent=1)
     print(text)
     if args.out:

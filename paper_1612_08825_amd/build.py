@@ -20,6 +20,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libttcconv.so")
 
 SOURCES = ["conv.hip", "fft.hip", "pyramid.hip", "ttc.hip", "ttc_variant.hip", "noalloc.hip", "ttcconv.cpp"]
+# the fused pass is built once per frame type (0 = u8, 1 = f16) and level count
+FUSED = [("ttc_fused.hip", f"ttc_fused_dt{dt}_l{lv}", [f"-DTC_FUSED_DT={dt}", f"-DTC_FUSED_LV={lv}"])
+         for dt in (1, 0) for lv in (4, 3, 2, 1)]
 
 ARCH = "gfx950"
 COMMON = [
@@ -42,9 +45,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job, verbose: bool) -> str:
+    src, name, defs = job if isinstance(job, tuple) else (job, os.path.basename(job), [])
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [hipcc(), *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,11 +59,13 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
     """Compile every HIP source for gfx950 and link libttcconv.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        # the slowest objects (the fused pass) first
+        objs = list(ex.map(lambda s: _compile(s, verbose), FUSED + SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

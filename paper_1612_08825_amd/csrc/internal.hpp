@@ -112,9 +112,11 @@ hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, v
 // ---------------------------------------------------------------- fused TTC
 // One entry of the device work table: a video stream and where its work and
 // results go.  The fused pass covers the stream with work items of one wave
-// each: a band of `band_rows` base rows by one column-wave of 480 owned base
-// columns (4 segments x 15 lanes x 8 columns).  Items are numbered
-// column-wave-major, band-minor, so consecutive items are vertically adjacent.
+// each: one frame pair on a band of `band_rows` base rows by one column-wave of
+// 504 owned base columns (63 lanes x 8 columns; lane 63 only lends its columns
+// to lane 62).  A (column-wave, band) is a "witem"; items are numbered
+// witem-major (column-wave-major, band-minor) and pair-minor, so the items of
+// consecutive pairs of one band are adjacent, then vertically adjacent bands.
 struct SeqDesc {
   const void* frame0;
   int64_t frame_stride;   // elements
@@ -124,8 +126,8 @@ struct SeqDesc {
   int32_t levels;
   int32_t band_rows;      // owned base rows per band (one wave)
   int32_t n_bands;        // ceil(H / band_rows)
-  int32_t n_cw;           // ceil(ceil((W - 1) / 120) / 4)
-  int32_t n_witems;       // work items (waves) per (pair, level) = n_bands * n_cw
+  int32_t n_cw;           // ceil((W - 1) / 504)
+  int32_t n_witems;       // bands x column-waves: partial sums per (pair, level)
   int64_t item_begin;     // first work item of this stream (prefix over streams)
   int64_t pair_begin;     // first global pair index of this stream
   int64_t partial_begin;  // first float of this stream's partial sums
@@ -133,8 +135,7 @@ struct SeqDesc {
   int32_t pad;
 };
 
-constexpr int kSegCols = 120;         // owned base columns per 16-lane segment
-constexpr int kWaveCols = 4 * kSegCols;
+constexpr int kWaveCols = 504;  // owned base columns per wave (63 lanes x 8)
 
 struct FusedLaunch {
   int dt;           // TC_U8 or TC_F16
@@ -152,6 +153,18 @@ struct FusedLaunch {
 };
 
 hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s);
+namespace fused {
+// One launcher per frame type (dt0 = u8, dt1 = f16) and level count, each built
+// from ttc_fused.hip in an object of its own.
+hipError_t launch_ttc_fused_dt0_l1(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt0_l2(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt0_l3(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt0_l4(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt1_l1(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt1_l2(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt1_l3(const FusedLaunch& f, hipStream_t s);
+hipError_t launch_ttc_fused_dt1_l4(const FusedLaunch& f, hipStream_t s);
+}  // namespace fused
 hipError_t launch_ttc_finish(const FusedLaunch& f, tc_ttc_level* out, tc_ttc_pick* picks, hipStream_t s);
 bool fused_variant_exists(int dt, int levels, int band_rows);
 hipError_t launch_ttc_reselect(const tc_ttc_level* levels, int64_t n_pairs, int L, int rule, tc_ttc_pick* picks,

@@ -1,0 +1,437 @@
+// Fused multi-scale time-to-contact pass for gfx950.
+//
+// What is computed (Time to Contact, Formulation and Results): for every
+// consecutive frame pair of a stream and every pyramid level l < LV, the ten
+// sums of the least-squares normal equations over all 2x2x2 first-difference
+// cubes of that level.  The FP64 solve, FOE, TTC and the multi-scale choice
+// follow in the finishing pass (ttc.hip).
+//
+// This file is compiled once per frame type and level count
+// (-DTC_FUSED_DT=0 for u8 frames, 1 for f16; -DTC_FUSED_LV=1..4), so that the
+// unrolled kernels build in parallel; each object exports one launcher.
+//
+// How (one persistent launch):
+//   * A work item is one wave and one frame pair: a band of RB base rows (RB a
+//     multiple of 8, a launch parameter) by 504 columns of one stream.  Lane i
+//     holds 8 adjacent base columns (one level-3 column); the column right of
+//     its last one comes from lane i + 1 by a whole-wave DPP shift, so lanes
+//     0..62 own cubes and lane 63 only lends its columns to lane 62.
+//   * The wave walks the band's rows top to bottom, reading the row of both
+//     frames of the pair, and forms the temporal sum S = P0 + P1 and difference
+//     D = P1 - P0 (for f16 frames one mixed-precision FMA each).  Rows are
+//     prefetched one group of 8 ahead into registers.  Work items are numbered
+//     pair-minor, so the items of consecutive pairs of one band run side by
+//     side on one XCD and the frame they share is fetched from memory about
+//     once (the second read is served by the caches).  Nothing is kept in LDS
+//     between rows, which leaves the occupancy to the register file.
+//   * Horizontal neighbour sums/differences of S and D give the derivative
+//     cube by one more vertical step.  Because the pyramid is linear, the 2x2
+//     sums of S and D at even columns *are* the next level's S and D (times 4),
+//     so all levels are built on the fly in registers; nothing is written but
+//     the sums.  Values are kept as un-normalised block sums; the powers of two
+//     are removed in FP64 at the end.
+//   * The walk continues 2^(LV-1) rows past the band (halo) so that the last
+//     owned cube row of every level has its lower neighbour: 8 halo rows per RB
+//     owned rows at four levels.
+//   * Each lane sums its cubes in FP32 over the band; at the end of the item
+//     the wave reduces its lanes (DPP within groups of 8 lanes, then the 8
+//     group totals through LDS) and writes one partial per (pair, level, band).
+//   * After every row's products the ten running sums of each level are tied
+//     to that point of the program (an empty asm that reads and writes them),
+//     which keeps the compiler from deferring the products of many rows and
+//     keeping all their derivatives alive at once.
+//
+// Units inside the kernel at level l (U = block sums of 4^l base pixels of S or D):
+//   hx = 2^(3l+2) E_x (per base px), hy likewise, ht = 2^(2l+2) E_t,
+//   g = x_l hx + y_l hy = 2^(2l+2) G with x_l, y_l the cube centre in level pixels.
+#include <math.h>
+
+#include <type_traits>
+
+#include "ttc_common.hpp"
+
+#if !defined(TC_FUSED_DT) || !defined(TC_FUSED_LV)
+#error "ttc_fused.hip is built once per frame type (TC_FUSED_DT) and level count (TC_FUSED_LV)"
+#endif
+
+namespace ttc {
+namespace fused {
+namespace {
+
+using T = std::conditional_t<TC_FUSED_DT == 0, uint8_t, _Float16>;
+constexpr int LV = TC_FUSED_LV;
+static_assert(LV >= 1 && LV <= 4, "one to four levels");
+constexpr int kGroup = 8;          // rows per unrolled group (one level-3 row)
+constexpr int kHalo = 1 << (LV - 1);  // rows walked past the band
+
+// Accumulate the cubes of one row of one level.  hd*, hs*, hD* are the horizontal
+// quantities of the previous (p) and current level rows.  EDGE: some lane of the
+// wave has a partial set of valid columns at this level; cubes at columns
+// c >= ncv then contribute zero (their derivatives are masked).
+template <int NC, bool EDGE>
+__device__ __forceinline__ void cubes(float (&acc)[10], const float (&hdp)[NC], const float (&hd)[NC],
+                                      const float (&hsp)[NC], const float (&hs)[NC], const float (&hDp)[NC],
+                                      const float (&hD)[NC], int ncv, const float (&xc)[NC], float y) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    float ex = hdp[c] + hd[c];
+    float ey = hs[c] - hsp[c];
+    float et = hDp[c] + hD[c];
+    if constexpr (EDGE) {
+      const bool ok = c < ncv;
+      ex = ok ? ex : 0.f;
+      ey = ok ? ey : 0.f;
+      et = ok ? et : 0.f;
+    }
+    const float g = fmaf(y, ey, xc[c] * ex);
+    acc[0] = fmaf(ex, ex, acc[0]);
+    acc[1] = fmaf(ex, ey, acc[1]);
+    acc[2] = fmaf(ey, ey, acc[2]);
+    acc[3] = fmaf(g, ex, acc[3]);
+    acc[4] = fmaf(g, ey, acc[4]);
+    acc[5] = fmaf(g, g, acc[5]);
+    acc[6] = fmaf(ex, et, acc[6]);
+    acc[7] = fmaf(ey, et, acc[7]);
+    acc[8] = fmaf(g, et, acc[8]);
+    acc[9] = fmaf(et, et, acc[9]);
+  }
+  // the row's contribution is complete here (see the file comment)
+#pragma unroll
+  for (int q = 0; q < 10; ++q) asm volatile("" : "+v"(acc[q]));
+}
+
+// Value of lane i + 1 of the wave (DPP wave_shl:1); lane 63 receives 0.
+__device__ __forceinline__ float from_right(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
+}
+
+// Horizontal quantities of one level row of NC columns, given its block sums U
+// (of S) and V (of D); the column right of the lane comes from lane + 1.
+template <int NC>
+__device__ __forceinline__ void horizontals(const float (&U)[NC], const float (&V)[NC], float (&hs)[NC],
+                                            float (&hd)[NC], float (&hD)[NC]) {
+  const float un = from_right(U[0]);
+  const float vn = from_right(V[0]);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const float ur = (c + 1 < NC) ? U[c + 1] : un;
+    const float vr = (c + 1 < NC) ? V[c + 1] : vn;
+    hs[c] = U[c] + ur;
+    hd[c] = ur - U[c];
+    hD[c] = V[c] + vr;
+  }
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// Which group of the band a row group is: the first (rows 0..7), one inside
+// the band, or the halo past it.  It decides, at compile time, which of the
+// level rows formed in the group close an owned cube row: a level-l cube row
+// lr (between level rows lr - 1 and lr) belongs to the band when
+// 1 <= lr <= RB / 2^l.
+enum GroupKind { kFirst = 0, kInner = 1, kHalo_ = 2 };
+
+template <int KIND>
+__device__ __forceinline__ constexpr bool owns(int j, int l) {
+  // j: row within the group; a level-l row is formed when (j + 1) % 2^l == 0
+  if (KIND == kFirst) return (j >> l) >= 1;
+  if (KIND == kInner) return true;
+  return (j >> l) == 0;  // halo: only the cube row closing on the band's last level row
+}
+
+// The walk state of one band: the previous level rows' horizontal quantities
+// and the running sums.
+struct Walk {
+  float acc[LV][10];
+  float hs0p[8], hd0p[8], hD0p[8];
+  float hs1p[4], hd1p[4], hD1p[4];
+  float hs2p[2], hd2p[2], hD2p[2];
+  float hs3p[1], hd3p[1], hD3p[1];
+};
+
+// One group of up to 8 rows: rows r0 + j for j < NJ.  a[j], b[j] hold row j of
+// the pair's two frames.  CHECK: rows at or below H are skipped (the bottom
+// band); yrow: the band's first row's ordinate at each level.
+template <int KIND, int NJ, bool EDGE, bool CHECK, typename LOAD>
+__device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T> (&b)[kGroup], LOAD&& refill,
+                                           int rows_left, int w0, const int (&ncv)[LV], const float (&xc0)[8],
+                                           const float (&xc1)[4], const float (&xc2)[2], const float (&xc3)[1],
+                                           const float (&yb)[LV]) {
+  static_for<0, NJ>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    // row j of this group is in (a[j], b[j]); refill them with row j of the
+    // next group while this one is walked
+    const Raw8<T> ca = a[j], cb = b[j];
+    refill(a[j], b[j], w0 + kGroup + j);
+    if (!CHECK || j < rows_left) {
+      const int w = w0 + j;  // row within the band
+      float S[8], D[8];
+      cb.sum_diff(ca, S, D);
+      float hs0[8], hd0[8], hD0[8];
+      horizontals<8>(S, D, hs0, hd0, hD0);
+      if constexpr (owns<KIND>(j, 0))
+        cubes<8, EDGE>(s.acc[0], s.hd0p, hd0, s.hs0p, hs0, s.hD0p, hD0, ncv[0], xc0, yb[0] + (float)w);
+      if constexpr (LV >= 2 && (j & 1) == 1) {
+        float U1[4], V1[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          U1[c] = s.hs0p[2 * c] + hs0[2 * c];
+          V1[c] = s.hD0p[2 * c] + hD0[2 * c];
+        }
+        float hs1[4], hd1[4], hD1[4];
+        horizontals<4>(U1, V1, hs1, hd1, hD1);
+        if constexpr (owns<KIND>(j, 1))
+          cubes<4, EDGE>(s.acc[1], s.hd1p, hd1, s.hs1p, hs1, s.hD1p, hD1, ncv[1], xc1, yb[1] + (float)(w >> 1));
+        if constexpr (LV >= 3 && (j & 3) == 3) {
+          float U2[2], V2[2];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            U2[c] = s.hs1p[2 * c] + hs1[2 * c];
+            V2[c] = s.hD1p[2 * c] + hD1[2 * c];
+          }
+          float hs2[2], hd2[2], hD2[2];
+          horizontals<2>(U2, V2, hs2, hd2, hD2);
+          if constexpr (owns<KIND>(j, 2))
+            cubes<2, EDGE>(s.acc[2], s.hd2p, hd2, s.hs2p, hs2, s.hD2p, hD2, ncv[2], xc2, yb[2] + (float)(w >> 2));
+          if constexpr (LV >= 4 && (j & 7) == 7) {
+            float U3[1], V3[1];
+            U3[0] = s.hs2p[0] + hs2[0];
+            V3[0] = s.hD2p[0] + hD2[0];
+            float hs3[1], hd3[1], hD3[1];
+            horizontals<1>(U3, V3, hs3, hd3, hD3);
+            if constexpr (owns<KIND>(j, 3))
+              cubes<1, EDGE>(s.acc[3], s.hd3p, hd3, s.hs3p, hs3, s.hD3p, hD3, ncv[3], xc3, yb[3] + (float)(w >> 3));
+            s.hs3p[0] = hs3[0];
+            s.hd3p[0] = hd3[0];
+            s.hD3p[0] = hD3[0];
+          }
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            s.hs2p[c] = hs2[c];
+            s.hd2p[c] = hd2[c];
+            s.hD2p[c] = hD2[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          s.hs1p[c] = hs1[c];
+          s.hd1p[c] = hd1[c];
+          s.hD1p[c] = hD1[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        s.hs0p[c] = hs0[c];
+        s.hd0p[c] = hd0[c];
+        s.hD0p[c] = hD0[c];
+      }
+    }
+  });
+}
+
+// One wave, one pair, one band: rows row0 .. row0 + RB + kHalo - 1 (fewer at
+// the bottom of the frame), walked in unrolled groups of 8 rows, so that no
+// load is carried across a loop back edge.  EDGE: some lane owns a partial
+// set of cube columns; CHECK: the band reaches the bottom of the frame or the
+// stream is not vector-aligned (rows and lane chunks are then loaded with
+// checks).  Returns the lane's running sums.
+template <int RB, bool EDGE, bool CHECK>
+__device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, int c_lane, int lane,
+                                          float (&out)[LV][10]) {
+  constexpr int NW = RB + kHalo;                       // rows walked
+  constexpr int NG = (NW + kGroup - 1) / kGroup;       // groups walked
+  static_assert(RB % kGroup == 0, "bands are whole groups");
+  const int H = d.H, W = d.W;
+  // valid cube columns of this lane per level, and the cube-centre coordinates
+  int ncv[LV];
+  float yb[LV];
+#pragma unroll
+  for (int l = 0; l < LV; ++l) {
+    const int j0 = c_lane >> l;
+    int n = (W >> l) - 1 - j0;
+    n = n < 0 ? 0 : (n > (8 >> l) ? (8 >> l) : n);
+    ncv[l] = (lane == 63) ? 0 : n;
+    yb[l] = (float)(row0 >> l) - (float)H / (float)(2 << l);
+  }
+  auto xbase = [&](int l) { return (float)((c_lane >> l) + 1) - (float)W / (float)(2 << l); };
+  float xc0[8], xc1[4], xc2[2], xc3[1];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) xc0[c] = xbase(0) + (float)c;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) xc1[c] = xbase(1) + (float)c;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) xc2[c] = xbase(2) + (float)c;
+  xc3[0] = xbase(3);
+
+  const int ncols = W - c_lane;  // pixels of this lane inside the image
+  // Lanes right of the image read the last aligned chunk of the row instead:
+  // every load is unconditional, and what those lanes hold only reaches cubes
+  // that are not valid.
+  const int c_load = c_lane < W ? c_lane : ((W - 1) >> 3) << 3;
+  const uint32_t coff = (uint32_t)c_load * (uint32_t)sizeof(T);
+  const int64_t rs_b = d.row_stride * (int64_t)sizeof(T);
+  const char* fa = reinterpret_cast<const char*>(d.frame0) +
+                   ((int64_t)pair * d.frame_stride + (int64_t)row0 * d.row_stride) * (int64_t)sizeof(T);
+  const char* fb = fa + d.frame_stride * (int64_t)sizeof(T);
+  // rows of this band that exist, walked: owned rows plus the halo
+  const int n_rows = (H - row0 < NW) ? H - row0 : NW;
+
+  auto load_row = [&](Raw8<T>& r, const char* base, int w) {
+    const T* p = reinterpret_cast<const T*>(base + (int64_t)w * rs_b + coff);
+    if constexpr (!CHECK) {
+      r.load(p);
+    } else {
+      const int row = row0 + w;
+      if (w < n_rows && ncols > 0) {
+        // a vector load may overrun column W only where a next row exists
+        if (d.vec && (ncols >= 8 || row < H - 1)) r.load(p);
+        else r.load_partial(p, ncols < 8 ? ncols : 8);
+      } else {
+        r.zero();
+      }
+    }
+  };
+
+  Walk s;
+#pragma unroll
+  for (int l = 0; l < LV; ++l)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) s.acc[l][q] = 0.f;
+
+  // a ring of one group of rows of each frame: row j of the group being walked
+  // is replaced by row j of the next group as soon as it has been read
+  Raw8<T> a[kGroup], b[kGroup];
+#pragma unroll
+  for (int j = 0; j < kGroup; ++j) {
+    if (j < NW) {
+      load_row(a[j], fa, j);
+      load_row(b[j], fb, j);
+    }
+  }
+  static_for<0, NG>([&](auto gc) {
+    constexpr int gi = decltype(gc)::value;
+    constexpr int KIND = gi == 0 ? kFirst : (gi * kGroup < RB ? kInner : kHalo_);
+    constexpr int NJ = (NW - gi * kGroup) < kGroup ? NW - gi * kGroup : kGroup;
+    auto refill = [&](Raw8<T>& ra, Raw8<T>& rb, int w) {
+      // w = gi * 8 + 8 + j, known at compile time after unrolling
+      if (w < NW) {
+        load_row(ra, fa, w);
+        load_row(rb, fb, w);
+      }
+    };
+    walk_group<KIND, NJ, EDGE, CHECK>(s, a, b, refill, n_rows - gi * kGroup, gi * kGroup, ncv, xc0, xc1, xc2, xc3,
+                                      yb);
+  });
+
+  // lanes that own no cube of a level contribute zero
+#pragma unroll
+  for (int l = 0; l < LV; ++l) {
+    const bool own = ncv[l] > 0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) out[l][q] = own ? s.acc[l][q] : 0.f;
+  }
+}
+
+template <int RB>
+__global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
+  constexpr int NV = LV * 10;
+  __shared__ float red[8 * NV];
+  const int lane = threadIdx.x;
+
+  const int G = gridDim.x;
+  const int g = blockIdx.x;
+  // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so give
+  // each XCD a contiguous run of items (the pairs of one band, and vertically
+  // adjacent bands, which share frames and halo rows).
+  const int64_t slot = (G % 8 == 0) ? (int64_t)(g % 8) * (G / 8) + g / 8 : g;
+
+  for (int64_t t = 0;; ++t) {
+    const int64_t item = t * G + slot;
+    if (item >= a.n_items) break;
+    const SeqDesc d = uniform(seq_for_item(a, item));
+    const int64_t local = item - d.item_begin;  // = witem * n_pairs + pair
+    const int n_pairs = d.n_frames - 1;
+    const int witem = (int)(local / n_pairs);
+    const int pair = (int)(local - (int64_t)witem * n_pairs);
+    const int cw = witem / d.n_bands;
+    const int band = witem - cw * d.n_bands;
+    const int row0 = band * RB;
+    const int c_lane = cw * kWaveCols + lane * 8;
+    // vector loads are safe when every walked row exists with one more below
+    // it (a lane chunk may run up to 7 pixels past column W)
+    const int64_t below = (int64_t)d.H - row0 - (RB + kHalo);
+    const bool check = !(d.vec && below >= 1);
+    // some lane owns a partial set of cube columns at some level
+    bool edge = false;
+#pragma unroll
+    for (int l = 0; l < LV; ++l) {
+      const int n = (d.W >> l) - 1 - (c_lane >> l);
+      edge = edge || (lane < 63 && n > 0 && n < (8 >> l));
+    }
+    edge = __any(edge);
+    float v[LV][10];
+    if (edge) {
+      if (check) band_pair<RB, true, true>(d, pair, row0, c_lane, lane, v);
+      else band_pair<RB, true, false>(d, pair, row0, c_lane, lane, v);
+    } else {
+      if (check) band_pair<RB, false, true>(d, pair, row0, c_lane, lane, v);
+      else band_pair<RB, false, false>(d, pair, row0, c_lane, lane, v);
+    }
+
+    // One partial per (pair, level, band): the 10 LV values are summed over
+    // groups of 8 lanes with three DPP steps, the 8 group totals pass through
+    // LDS, and lane t < 10 LV adds the 8 totals of value t (= l * 10 + q).
+    float r[NV];
+#pragma unroll
+    for (int l = 0; l < LV; ++l)
+#pragma unroll
+      for (int q = 0; q < 10; ++q) r[l * 10 + q] = v[l][q];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) r[i] += dpp_f32<kDppQuadXor1>(r[i]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) r[i] += dpp_f32<kDppQuadXor2>(r[i]);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) r[i] += dpp_f32<kDppRowHalfMirror>(r[i]);
+    __syncthreads();  // the previous item's reads of `red` are done
+    if ((lane & 7) == 0) {
+#pragma unroll
+      for (int i = 0; i < NV; ++i) red[(lane >> 3) * NV + i] = r[i];
+    }
+    __syncthreads();
+    if (lane < NV) {
+      float tot = red[lane];
+#pragma unroll
+      for (int gi = 1; gi < 8; ++gi) tot += red[gi * NV + lane];
+      const int l = lane / 10, q = lane - (lane / 10) * 10;
+      float* part = a.partials + d.partial_begin;
+      as_global(part)[((int64_t)(pair * LV + l) * d.n_witems + witem) * 10 + q] = tot;
+    }
+  }
+}
+
+}  // namespace
+
+#define TC_CAT3(a, b, c) a##b##c
+#define TC_LAUNCHER(dt, lv) TC_CAT3(launch_ttc_fused_dt, dt, _l##lv)
+#define TC_LAUNCHER_X(dt, lv) TC_LAUNCHER(dt, lv)
+
+hipError_t TC_LAUNCHER_X(TC_FUSED_DT, TC_FUSED_LV)(const FusedLaunch& f, hipStream_t s) {
+  const FusedArgs a = make_args(f);
+  const dim3 grid((unsigned)f.grid), block(64);
+  switch (f.band_rows) {
+    case 8: hipLaunchKernelGGL(ttc_fused<8>, grid, block, 0, s, a); break;
+    case 16: hipLaunchKernelGGL(ttc_fused<16>, grid, block, 0, s, a); break;
+    case 32: hipLaunchKernelGGL(ttc_fused<32>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fused
+}  // namespace ttc

@@ -631,12 +631,13 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // 64-stream u8 mix at 3 levels): f16 best at 8 rows x 64 groups/CU (16 and 32
 // rows hold too much LDS per wave), u8 best at 16 rows x 32 groups/CU.  More
 // groups than items means one item per work-group, dispatched by the hardware.
+// The tuning sweep's best launch shape per frame type and level count on
+// MI355X (f16: the 64-stream batched workload; u8: a 64-stream serving mix).
 tc_ttc_tuning default_tuning(int dtype, int levels) {
-  (void)levels;
-  tc_ttc_tuning t;
-  t.band_rows = dtype == TC_U8 ? 16 : 8;
-  t.groups_per_cu = dtype == TC_U8 ? 32 : 64;
-  return t;
+  static const tc_ttc_tuning f16[TC_MAX_LEVELS] = {{32, 128}, {32, 16}, {32, 16}, {32, 128}};
+  static const tc_ttc_tuning u8[TC_MAX_LEVELS] = {{16, 32}, {32, 16}, {32, 16}, {32, 16}};
+  const int l = levels < 1 ? 0 : (levels > TC_MAX_LEVELS ? TC_MAX_LEVELS - 1 : levels - 1);
+  return dtype == TC_U8 ? u8[l] : f16[l];
 }
 
 bool tuning_ok(const tc_ttc_tuning& t, int dtype, int levels) {
@@ -674,8 +675,7 @@ void fill_desc(SeqDesc& d, const tc_seq& q, int dtype, int band_rows) {
   d.levels = q.levels;
   d.band_rows = band_rows;
   d.n_bands = (q.H + band_rows - 1) / band_rows;
-  const int n_seg = (q.W - 1 + kSegCols - 1) / kSegCols;
-  d.n_cw = (n_seg + 3) / 4;
+  d.n_cw = (q.W - 1 + kWaveCols - 1) / kWaveCols;
   d.n_witems = d.n_bands * d.n_cw;
   d.pad = 0;
   d.vec = vector_ok(q, dtype);
@@ -704,7 +704,7 @@ static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
     d.item_begin = items;
     d.pair_begin = pairs;
     d.partial_begin = floats;
-    items += d.n_witems;
+    items += (int64_t)d.n_witems * (d.n_frames - 1);  // one work item per (band, pair)
     pairs += d.n_frames - 1;
     floats += (int64_t)(d.n_frames - 1) * p->levels * d.n_witems * 10;
   }
@@ -729,7 +729,7 @@ static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
   int32_t* pair_seq = reinterpret_cast<int32_t*>(base + desc_bytes + item_bytes);
   for (int i = 0; i < n_seqs; ++i) {
     const SeqDesc& d = descs[(size_t)i];
-    for (int64_t k = 0; k < d.n_witems; ++k) item_seq[d.item_begin + k] = i;
+    for (int64_t k = 0; k < (int64_t)d.n_witems * (d.n_frames - 1); ++k) item_seq[d.item_begin + k] = i;
     for (int64_t k = 0; k < d.n_frames - 1; ++k) pair_seq[d.pair_begin + k] = i;
   }
   p->n_seqs = n_seqs;

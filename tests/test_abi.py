@@ -235,10 +235,12 @@ def test_ttc_plan_validation(lib):
 
 def test_ttc_tuning_defaults_and_rejections(lib):
     t = L.TcTuning()
-    assert lib.tc_ttc_tuning_default(L.TC_F16, 4, C.byref(t)) == 0
-    assert (t.band_rows, t.groups_per_cu) == (8, 64)
-    assert lib.tc_ttc_tuning_default(L.TC_U8, 3, C.byref(t)) == 0
-    assert (t.band_rows, t.groups_per_cu) == (16, 32)
+    # the sweep's choices, per frame type and level count
+    want = {(L.TC_F16, 4): (32, 128), (L.TC_F16, 3): (32, 16), (L.TC_F16, 1): (32, 128), (L.TC_U8, 3): (32, 16),
+            (L.TC_U8, 1): (16, 32)}
+    for (dt, lv), shape in want.items():
+        assert lib.tc_ttc_tuning_default(dt, lv, C.byref(t)) == 0
+        assert (t.band_rows, t.groups_per_cu) == shape, (dt, lv)
     assert lib.tc_ttc_tuning_default(L.TC_F32, 3, C.byref(t)) == L.TC_EDTYPE
     h = C.c_void_p()
     arr = (L.TcSeq * 1)(_seq(64, 64, levels=3))
