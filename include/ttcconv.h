@@ -314,8 +314,9 @@ typedef struct {
 
 /* A video stream of n_frames frames of H x W pixels.  Frame k starts at
  * frame0 + k * frame_stride elements and row i of it at + i * row_stride.
- * Pairs (k, k+1), k = 0 .. n_frames-2, are processed; each frame is read from
- * memory once per pass.  A single pair of unrelated frames is a stream with
+ * Pairs (k, k+1), k = 0 .. n_frames-2, are processed; a frame is read by the
+ * two pairs it belongs to, whose work runs side by side (the second read is
+ * normally served by the caches).  A single pair of unrelated frames is a stream with
  * n_frames = 2 and frame_stride = next - prev (in elements, may be negative). */
 typedef struct {
   const void* frame0;
@@ -339,12 +340,13 @@ typedef struct tc_ttc_plan tc_ttc_plan;
  * pair_base(s) = sum over earlier streams of (n_frames - 1). */
 int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan);
 
-/* Launch shape of the fused pass.  band_rows: base rows owned by one wave
- * (8, 16 or 32; taller bands walk fewer halo rows per owned row but need more
- * LDS per wave); groups_per_cu: work-groups (one wave each) of the persistent
- * grid per compute unit (1..256).  The sums depend on band_rows through their
- * blocking (not on groups_per_cu); a fixed tuning gives bit-identical results
- * for a stream whatever else is in the batch. */
+/* Launch shape of the fused pass.  band_rows: base rows one wave walks for
+ * one frame pair (a multiple of 16 from 16 to 256; taller bands walk fewer
+ * halo rows per owned row and give fewer, longer work items); groups_per_cu:
+ * work-groups (one wave each) of the persistent grid per compute unit
+ * (1..256).  The sums depend on band_rows through their blocking (not on
+ * groups_per_cu); a fixed tuning gives bit-identical results for a stream
+ * whatever else is in the batch. */
 typedef struct {
   int32_t band_rows;
   int32_t groups_per_cu;
@@ -452,8 +454,8 @@ int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_t levels, v
  * sums go to a scratch array of TC_NOALLOC_SCRATCH_BYTES (4 MiB) held in the
  * library's device memory, one copy per GPU, kept until the process ends.  A
  * pair whose workspace (tc_ttc_workspace_size) exceeds that is rejected with
- * TC_ENOMEM before anything is launched (square frames up to 9984 x 9984
- * with 4 levels, 19968 x 19968 with one).  The first call on a device looks up the array's address on
+ * TC_ENOMEM before anything is launched (square frames up to 14448 x 14448
+ * with 4 levels, 28912 x 28912 with one).  The first call on a device looks up the array's address on
  * the current device (the stream must belong to it); nothing is allocated or
  * freed, by this call or its kernels.  Every call on one GPU shares that GPU's
  * array: calls that overlap on one GPU (two streams, or two host threads)

@@ -2,7 +2,7 @@
 
 For a (dtype, levels) class the sweep times the fused kernel over a
 representative batch for every candidate launch shape -- band height (rows a
-wave owns: 8, 16, 32) and persistent work-groups per compute unit -- with HIP
+wave walks for one pair: 16, 32, 64, 128) and persistent work-groups per compute unit -- with HIP
 events on the launch stream, and keeps the fastest.  Candidates that fail to
 create a plan are skipped.  The table it prints is what the library's built-in
 default (``tc_ttc_tuning_default``) is set from; callers can also pass a tuning
@@ -17,7 +17,7 @@ import json
 import sys
 from typing import Dict, List, Sequence, Tuple
 
-BAND_ROWS = (8, 16, 32)
+BAND_ROWS = (16, 32, 64, 128)
 GROUPS_PER_CU = (8, 16, 32, 64, 128)
 
 

@@ -96,37 +96,6 @@ template <> struct Raw8<_Float16> {
       f[c] = (float)__builtin_bit_cast(_Float16, h);
     }
   }
-  // Temporal sum and difference with the same pixels of the previous frame:
-  // S = old + this, D = this - old, in FP32 with one rounding each.
-  //
-  // v_fma_mix_f32 converts its f16 operands (either half of a dword, chosen by
-  // op_sel) to FP32 exactly and computes a * 1.0 + c with a single rounding, so
-  // one instruction gives what a conversion of each operand and an FP32 add
-  // give in three.  The compiler does not form it by itself here.
-  //
-  // Column 0 is computed in plain code: its S and D are the ones a DPP move
-  // reads next (the right neighbour of the lane to the left), and the hazard
-  // check that spaces a VALU write from a DPP read of the same register does
-  // not see writes made inside inline assembly.
-  __device__ __forceinline__ void sum_diff(const Raw8& old, float (&S)[8], float (&D)[8]) const {
-    {
-      const float a = (float)__builtin_bit_cast(_Float16, (uint16_t)(old.d[0] & 0xffffu));
-      const float b = (float)__builtin_bit_cast(_Float16, (uint16_t)(d[0] & 0xffffu));
-      S[0] = a + b;
-      D[0] = b - a;
-    }
-    asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(S[1]) : "v"(d[0]), "v"(old.d[0]));
-    asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(D[1]) : "v"(d[0]), "v"(old.d[0]));
-#pragma unroll
-    for (int i = 1; i < 4; ++i) {
-      asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,1]" : "=v"(S[2 * i]) : "v"(d[i]), "v"(old.d[i]));
-      asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel_hi:[1,0,1]" : "=v"(D[2 * i]) : "v"(d[i]), "v"(old.d[i]));
-      asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(S[2 * i + 1]) : "v"(d[i]),
-          "v"(old.d[i]));
-      asm("v_fma_mix_f32 %0, %1, 1.0, -%2 op_sel:[1,0,1] op_sel_hi:[1,0,1]" : "=v"(D[2 * i + 1]) : "v"(d[i]),
-          "v"(old.d[i]));
-    }
-  }
 };
 
 // ---- error-free transformations ---------------------------------------------

@@ -124,8 +124,8 @@ __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __r
 }  // namespace
 
 bool fused_variant_exists(int dt, int levels, int band_rows) {
-  return (dt == TC_U8 || dt == TC_F16) && levels >= 1 && levels <= 4 &&
-         (band_rows == 8 || band_rows == 16 || band_rows == 32);
+  return (dt == TC_U8 || dt == TC_F16) && levels >= 1 && levels <= 4 && band_rows >= 16 && band_rows <= 256 &&
+         band_rows % 16 == 0;
 }
 
 hipError_t launch_ttc_fused(const FusedLaunch& f, hipStream_t s) {

@@ -18,6 +18,7 @@ struct FusedArgs {
   int64_t n_items;
   int64_t n_pairs;
   float* partials;
+  float one;  // 1.0, passed in so that mixed-precision FMAs by one are not folded away
 };
 
 // Every field of a descriptor read by a whole wave is the same in all lanes;
@@ -95,6 +96,7 @@ inline FusedArgs make_args(const FusedLaunch& f) {
   a.n_items = f.n_items;
   a.n_pairs = f.n_pairs;
   a.partials = f.partials;
+  a.one = 1.0f;
   return a;
 }
 

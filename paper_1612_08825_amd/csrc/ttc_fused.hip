@@ -8,34 +8,35 @@
 //
 // This file is compiled once per frame type and level count
 // (-DTC_FUSED_DT=0 for u8 frames, 1 for f16; -DTC_FUSED_LV=1..4), so that the
-// unrolled kernels build in parallel; each object exports one launcher.
+// kernels build in parallel; each object exports one launcher.
 //
 // How (one persistent launch):
 //   * A work item is one wave and one frame pair: a band of RB base rows (RB a
-//     multiple of 8, a launch parameter) by 504 columns of one stream.  Lane i
+//     multiple of 16, a launch parameter) by 504 columns of one stream.  Lane i
 //     holds 8 adjacent base columns (one level-3 column); the column right of
 //     its last one comes from lane i + 1 by a whole-wave DPP shift, so lanes
 //     0..62 own cubes and lane 63 only lends its columns to lane 62.
 //   * The wave walks the band's rows top to bottom, reading the row of both
 //     frames of the pair, and forms the temporal sum S = P0 + P1 and difference
 //     D = P1 - P0 (for f16 frames one mixed-precision FMA each).  Rows are
-//     prefetched one group of 8 ahead into registers.  Work items are numbered
-//     pair-minor, so the items of consecutive pairs of one band run side by
-//     side on one XCD and the frame they share is fetched from memory about
-//     once (the second read is served by the caches).  Nothing is kept in LDS
-//     between rows, which leaves the occupancy to the register file.
+//     prefetched eight ahead through a register ring: row j's registers are
+//     refilled with row j + 8 as soon as its S and D are formed.  Work items
+//     are numbered pair-minor, so the items of consecutive pairs of one band
+//     run side by side on one XCD and the frame they share is fetched from
+//     memory about once (the second read is served by the caches).
 //   * Horizontal neighbour sums/differences of S and D give the derivative
 //     cube by one more vertical step.  Because the pyramid is linear, the 2x2
 //     sums of S and D at even columns *are* the next level's S and D (times 4),
 //     so all levels are built on the fly in registers; nothing is written but
 //     the sums.  Values are kept as un-normalised block sums; the powers of two
 //     are removed in FP64 at the end.
-//   * The walk continues 2^(LV-1) rows past the band (halo) so that the last
-//     owned cube row of every level has its lower neighbour: 8 halo rows per RB
-//     owned rows at four levels.
-//   * Each lane sums its cubes in FP32 over the band; at the end of the item
-//     the wave reduces its lanes (DPP within groups of 8 lanes, then the 8
-//     group totals through LDS) and writes one partial per (pair, level, band).
+//   * Rows go in groups of 8 (one level-3 row): the first group, a loop over
+//     the groups inside the band, and the halo past it, 2^(LV-1) rows, so that
+//     the last owned cube row of every level has its lower neighbour.
+//   * Each lane sums its cubes in FP32 registers and adds the block into its
+//     own LDS slots every 16 rows; at the end of the item the wave reduces its
+//     lanes (DPP within groups of 8 lanes, then the 8 group totals through
+//     LDS) and writes one partial per (pair, level, band).
 //   * After every row's products the ten running sums of each level are tied
 //     to that point of the program (an empty asm that reads and writes them),
 //     which keeps the compiler from deferring the products of many rows and
@@ -61,8 +62,29 @@ namespace {
 using T = std::conditional_t<TC_FUSED_DT == 0, uint8_t, _Float16>;
 constexpr int LV = TC_FUSED_LV;
 static_assert(LV >= 1 && LV <= 4, "one to four levels");
-constexpr int kGroup = 8;          // rows per unrolled group (one level-3 row)
+constexpr int kGroup = 8;             // rows per unrolled group (one level-3 row)
 constexpr int kHalo = 1 << (LV - 1);  // rows walked past the band
+constexpr int NV = LV * 10;           // running sums per lane
+
+// Temporal sum and difference of eight pixels of two frames, S = a + b and
+// D = b - a in FP32.  u8: exact conversions and exact sums.  f16: one
+// mixed-precision FMA each (both halves converted exactly, one rounding), with
+// `one` = 1.0 held in a register so that the multiply is not folded away.
+__device__ __forceinline__ void sum_diff(const Raw8<uint8_t>& a, const Raw8<uint8_t>& b, float (&S)[8],
+                                         float (&D)[8], float) {
+  b.sum_diff(a, S, D);
+}
+__device__ __forceinline__ void sum_diff(const Raw8<_Float16>& a, const Raw8<_Float16>& b, float (&S)[8],
+                                         float (&D)[8], float one) {
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const uint32_t sh = 16 * (c & 1);
+    const float av = (float)__builtin_bit_cast(_Float16, (uint16_t)(a.d[c >> 1] >> sh));
+    const float bv = (float)__builtin_bit_cast(_Float16, (uint16_t)(b.d[c >> 1] >> sh));
+    S[c] = __builtin_fmaf(bv, one, av);
+    D[c] = __builtin_fmaf(bv, one, -av);
+  }
+}
 
 // Accumulate the cubes of one row of one level.  hd*, hs*, hD* are the horizontal
 // quantities of the previous (p) and current level rows.  EDGE: some lane of the
@@ -135,7 +157,7 @@ __device__ __forceinline__ void static_for(F&& f) {
 // level rows formed in the group close an owned cube row: a level-l cube row
 // lr (between level rows lr - 1 and lr) belongs to the band when
 // 1 <= lr <= RB / 2^l.
-enum GroupKind { kFirst = 0, kInner = 1, kHalo_ = 2 };
+enum GroupKind { kFirst = 0, kInner = 1, kHaloGroup = 2 };
 
 template <int KIND>
 __device__ __forceinline__ constexpr bool owns(int j, int l) {
@@ -145,38 +167,39 @@ __device__ __forceinline__ constexpr bool owns(int j, int l) {
   return (j >> l) == 0;  // halo: only the cube row closing on the band's last level row
 }
 
-// The walk state of one band: the previous level rows' horizontal quantities
-// and the running sums.
+// The walk state of one band: the previous level rows' horizontal quantities,
+// the running sums, and the ordinate of the current group's first row per level.
 struct Walk {
   float acc[LV][10];
   float hs0p[8], hd0p[8], hD0p[8];
   float hs1p[4], hd1p[4], hD1p[4];
   float hs2p[2], hd2p[2], hD2p[2];
   float hs3p[1], hd3p[1], hD3p[1];
+  float y[LV];
 };
 
-// One group of up to 8 rows: rows r0 + j for j < NJ.  a[j], b[j] hold row j of
-// the pair's two frames.  CHECK: rows at or below H are skipped (the bottom
-// band); yrow: the band's first row's ordinate at each level.
-template <int KIND, int NJ, bool EDGE, bool CHECK, typename LOAD>
-__device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T> (&b)[kGroup], LOAD&& refill,
-                                           int rows_left, int w0, const int (&ncv)[LV], const float (&xc0)[8],
+// One group of NJ (<= 8) rows.  a[j], b[j] hold row j of the pair's two frames;
+// refill(a[j], b[j], j) loads row j of the next group into them once row j's S
+// and D are formed.  CHECK: rows j >= rows_left do not exist (the bottom band).
+template <int KIND, int NJ, bool EDGE, bool CHECK, typename REFILL>
+__device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T> (&b)[kGroup], REFILL&& refill,
+                                           int rows_left, const int (&ncv)[LV], const float (&xc0)[8],
                                            const float (&xc1)[4], const float (&xc2)[2], const float (&xc3)[1],
-                                           const float (&yb)[LV]) {
+                                           float one) {
   static_for<0, NJ>([&](auto jc) {
     constexpr int j = decltype(jc)::value;
-    // row j of this group is in (a[j], b[j]); refill them with row j of the
-    // next group while this one is walked
-    const Raw8<T> ca = a[j], cb = b[j];
-    refill(a[j], b[j], w0 + kGroup + j);
+    float S[8], D[8];
+    sum_diff(a[j], b[j], S, D, one);
+    // the row's registers are free only now: keep the refill behind the reads
+    // (a load hoisted above them would need other registers, and a copy back
+    // at the loop's back edge that waits for every load in flight)
+    asm volatile("" ::"v"(S[7]), "v"(D[7]), "v"(S[6]), "v"(D[6]) : "memory");
+    refill(a[j], b[j], j);
     if (!CHECK || j < rows_left) {
-      const int w = w0 + j;  // row within the band
-      float S[8], D[8];
-      cb.sum_diff(ca, S, D);
       float hs0[8], hd0[8], hD0[8];
       horizontals<8>(S, D, hs0, hd0, hD0);
       if constexpr (owns<KIND>(j, 0))
-        cubes<8, EDGE>(s.acc[0], s.hd0p, hd0, s.hs0p, hs0, s.hD0p, hD0, ncv[0], xc0, yb[0] + (float)w);
+        cubes<8, EDGE>(s.acc[0], s.hd0p, hd0, s.hs0p, hs0, s.hD0p, hD0, ncv[0], xc0, s.y[0] + (float)j);
       if constexpr (LV >= 2 && (j & 1) == 1) {
         float U1[4], V1[4];
 #pragma unroll
@@ -187,7 +210,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
         float hs1[4], hd1[4], hD1[4];
         horizontals<4>(U1, V1, hs1, hd1, hD1);
         if constexpr (owns<KIND>(j, 1))
-          cubes<4, EDGE>(s.acc[1], s.hd1p, hd1, s.hs1p, hs1, s.hD1p, hD1, ncv[1], xc1, yb[1] + (float)(w >> 1));
+          cubes<4, EDGE>(s.acc[1], s.hd1p, hd1, s.hs1p, hs1, s.hD1p, hD1, ncv[1], xc1, s.y[1] + (float)(j >> 1));
         if constexpr (LV >= 3 && (j & 3) == 3) {
           float U2[2], V2[2];
 #pragma unroll
@@ -198,7 +221,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
           float hs2[2], hd2[2], hD2[2];
           horizontals<2>(U2, V2, hs2, hd2, hD2);
           if constexpr (owns<KIND>(j, 2))
-            cubes<2, EDGE>(s.acc[2], s.hd2p, hd2, s.hs2p, hs2, s.hD2p, hD2, ncv[2], xc2, yb[2] + (float)(w >> 2));
+            cubes<2, EDGE>(s.acc[2], s.hd2p, hd2, s.hs2p, hs2, s.hD2p, hD2, ncv[2], xc2, s.y[2] + (float)(j >> 2));
           if constexpr (LV >= 4 && (j & 7) == 7) {
             float U3[1], V3[1];
             U3[0] = s.hs2p[0] + hs2[0];
@@ -206,7 +229,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
             float hs3[1], hd3[1], hD3[1];
             horizontals<1>(U3, V3, hs3, hd3, hD3);
             if constexpr (owns<KIND>(j, 3))
-              cubes<1, EDGE>(s.acc[3], s.hd3p, hd3, s.hs3p, hs3, s.hD3p, hD3, ncv[3], xc3, yb[3] + (float)(w >> 3));
+              cubes<1, EDGE>(s.acc[3], s.hd3p, hd3, s.hs3p, hs3, s.hD3p, hD3, ncv[3], xc3, s.y[3]);
             s.hs3p[0] = hs3[0];
             s.hd3p[0] = hd3[0];
             s.hD3p[0] = hD3[0];
@@ -233,31 +256,49 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
       }
     }
   });
+  // the next group's first row, per level
+#pragma unroll
+  for (int l = 0; l < LV; ++l) s.y[l] += (float)(kGroup >> l);
+}
+
+// Adds the register block of running sums into the lane's own LDS slots
+// (read, FP32 add, write back; no other lane touches them) and clears it, so
+// that each FP32 register block holds at most 16 rows of products.
+__device__ __forceinline__ void flush(Walk& s, float* tot, int lane) {
+  float t[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) t[i] = tot[i * 64 + lane];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) tot[i * 64 + lane] = t[i] + s.acc[i / 10][i % 10];
+#pragma unroll
+  for (int l = 0; l < LV; ++l)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) s.acc[l][q] = 0.f;
 }
 
 // One wave, one pair, one band: rows row0 .. row0 + RB + kHalo - 1 (fewer at
-// the bottom of the frame), walked in unrolled groups of 8 rows, so that no
-// load is carried across a loop back edge.  EDGE: some lane owns a partial
-// set of cube columns; CHECK: the band reaches the bottom of the frame or the
-// stream is not vector-aligned (rows and lane chunks are then loaded with
-// checks).  Returns the lane's running sums.
-template <int RB, bool EDGE, bool CHECK>
-__device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, int c_lane, int lane,
-                                          float (&out)[LV][10]) {
-  constexpr int NW = RB + kHalo;                       // rows walked
-  constexpr int NG = (NW + kGroup - 1) / kGroup;       // groups walked
-  static_assert(RB % kGroup == 0, "bands are whole groups");
+// the bottom of the frame).  EDGE: some lane owns a partial set of cube
+// columns; CHECK: the band reaches the bottom of the frame or the stream is
+// not vector-aligned (rows and lane chunks are then loaded with checks).
+// Leaves the lane's sums in tot[(l * 10 + q) * 64 + lane] (zero for a level at
+// which the lane owns no cube).
+template <bool EDGE, bool CHECK>
+__device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, int RB, int c_lane, int lane,
+                                          float* tot, float one) {
   const int H = d.H, W = d.W;
+  const int NW = RB + kHalo;  // rows walked
   // valid cube columns of this lane per level, and the cube-centre coordinates
   int ncv[LV];
-  float yb[LV];
+  Walk s;
 #pragma unroll
   for (int l = 0; l < LV; ++l) {
     const int j0 = c_lane >> l;
     int n = (W >> l) - 1 - j0;
     n = n < 0 ? 0 : (n > (8 >> l) ? (8 >> l) : n);
     ncv[l] = (lane == 63) ? 0 : n;
-    yb[l] = (float)(row0 >> l) - (float)H / (float)(2 << l);
+    // ordinate of the cube row closing on the band's first level row: the cube
+    // between level rows i - 1 and i has its centre at 2^l i - H/2 base pixels
+    s.y[l] = (float)(row0 >> l) - (float)H / (float)(2 << l);
   }
   auto xbase = [&](int l) { return (float)((c_lane >> l) + 1) - (float)W / (float)(2 << l); };
   float xc0[8], xc1[4], xc2[2], xc3[1];
@@ -276,6 +317,7 @@ __device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, 
   const int c_load = c_lane < W ? c_lane : ((W - 1) >> 3) << 3;
   const uint32_t coff = (uint32_t)c_load * (uint32_t)sizeof(T);
   const int64_t rs_b = d.row_stride * (int64_t)sizeof(T);
+  // the band's first row of each frame (uniform across the wave)
   const char* fa = reinterpret_cast<const char*>(d.frame0) +
                    ((int64_t)pair * d.frame_stride + (int64_t)row0 * d.row_stride) * (int64_t)sizeof(T);
   const char* fb = fa + d.frame_stride * (int64_t)sizeof(T);
@@ -298,49 +340,60 @@ __device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, 
     }
   };
 
-  Walk s;
 #pragma unroll
   for (int l = 0; l < LV; ++l)
 #pragma unroll
     for (int q = 0; q < 10; ++q) s.acc[l][q] = 0.f;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) tot[i * 64 + lane] = 0.f;
 
-  // a ring of one group of rows of each frame: row j of the group being walked
-  // is replaced by row j of the next group as soon as it has been read
+  // the ring: rows 0..7, then each row j replaced by row j + 8 once read; the
+  // rows refilled in the last inner group are the halo's (a row index past the
+  // walk is clamped to its last row: loaded, never used)
   Raw8<T> a[kGroup], b[kGroup];
 #pragma unroll
   for (int j = 0; j < kGroup; ++j) {
-    if (j < NW) {
-      load_row(a[j], fa, j);
-      load_row(b[j], fb, j);
-    }
+    load_row(a[j], fa, j);
+    load_row(b[j], fb, j);
   }
-  static_for<0, NG>([&](auto gc) {
-    constexpr int gi = decltype(gc)::value;
-    constexpr int KIND = gi == 0 ? kFirst : (gi * kGroup < RB ? kInner : kHalo_);
-    constexpr int NJ = (NW - gi * kGroup) < kGroup ? NW - gi * kGroup : kGroup;
-    auto refill = [&](Raw8<T>& ra, Raw8<T>& rb, int w) {
-      // w = gi * 8 + 8 + j, known at compile time after unrolling
-      if (w < NW) {
-        load_row(ra, fa, w);
-        load_row(rb, fb, w);
-      }
-    };
-    walk_group<KIND, NJ, EDGE, CHECK>(s, a, b, refill, n_rows - gi * kGroup, gi * kGroup, ncv, xc0, xc1, xc2, xc3,
-                                      yb);
-  });
+  int gw = kGroup;  // first row of the next group
+  auto refill = [&](Raw8<T>& ra, Raw8<T>& rb, int j) {
+    const int w = gw + j < NW ? gw + j : NW - 1;
+    load_row(ra, fa, w);
+    load_row(rb, fb, w);
+  };
+  auto none = [&](Raw8<T>&, Raw8<T>&, int) {};
 
+  walk_group<kFirst, kGroup, EDGE, CHECK>(s, a, b, refill, n_rows, ncv, xc0, xc1, xc2, xc3, one);
+  // groups 1 .. inner_end - 1 lie inside the band, group inner_end is the halo
+  const int inner_end = RB / kGroup;
+  for (int g = 1; g < inner_end; ++g) {
+    gw += kGroup;
+    walk_group<kInner, kGroup, EDGE, CHECK>(s, a, b, refill, n_rows - g * kGroup, ncv, xc0, xc1, xc2, xc3, one);
+    if (g & 1) flush(s, tot, lane);
+  }
+  walk_group<kHaloGroup, kHalo, EDGE, CHECK>(s, a, b, none, n_rows - inner_end * kGroup, ncv, xc0, xc1, xc2, xc3,
+                                             one);
   // lanes that own no cube of a level contribute zero
 #pragma unroll
   for (int l = 0; l < LV; ++l) {
-    const bool own = ncv[l] > 0;
+    if (ncv[l] == 0) {
 #pragma unroll
-    for (int q = 0; q < 10; ++q) out[l][q] = own ? s.acc[l][q] : 0.f;
+      for (int q = 0; q < 10; ++q) s.acc[l][q] = 0.f;
+    }
+  }
+  flush(s, tot, lane);
+#pragma unroll
+  for (int l = 0; l < LV; ++l) {
+    if (ncv[l] == 0) {
+#pragma unroll
+      for (int q = 0; q < 10; ++q) tot[(l * 10 + q) * 64 + lane] = 0.f;
+    }
   }
 }
 
-template <int RB>
-__global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
-  constexpr int NV = LV * 10;
+__global__ __launch_bounds__(64) void ttc_fused(FusedArgs a, int RB) {
+  __shared__ float tot[NV * 64];  // each lane's running sums, [value][lane]
   __shared__ float red[8 * NV];
   const int lane = threadIdx.x;
 
@@ -375,23 +428,22 @@ __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
       edge = edge || (lane < 63 && n > 0 && n < (8 >> l));
     }
     edge = __any(edge);
-    float v[LV][10];
     if (edge) {
-      if (check) band_pair<RB, true, true>(d, pair, row0, c_lane, lane, v);
-      else band_pair<RB, true, false>(d, pair, row0, c_lane, lane, v);
+      if (check) band_pair<true, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+      else band_pair<true, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
     } else {
-      if (check) band_pair<RB, false, true>(d, pair, row0, c_lane, lane, v);
-      else band_pair<RB, false, false>(d, pair, row0, c_lane, lane, v);
+      if (check) band_pair<false, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+      else band_pair<false, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
     }
 
     // One partial per (pair, level, band): the 10 LV values are summed over
     // groups of 8 lanes with three DPP steps, the 8 group totals pass through
     // LDS, and lane t < 10 LV adds the 8 totals of value t (= l * 10 + q).
+    // (A wave reads back only its own LDS writes: LDS runs one wave's
+    // operations in order, and the compiler waits for the reads' data.)
     float r[NV];
 #pragma unroll
-    for (int l = 0; l < LV; ++l)
-#pragma unroll
-      for (int q = 0; q < 10; ++q) r[l * 10 + q] = v[l][q];
+    for (int i = 0; i < NV; ++i) r[i] = tot[i * 64 + lane];
 #pragma unroll
     for (int i = 0; i < NV; ++i) r[i] += dpp_f32<kDppQuadXor1>(r[i]);
 #pragma unroll
@@ -405,12 +457,12 @@ __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
     }
     __syncthreads();
     if (lane < NV) {
-      float tot = red[lane];
+      float sum = red[lane];
 #pragma unroll
-      for (int gi = 1; gi < 8; ++gi) tot += red[gi * NV + lane];
+      for (int gi = 1; gi < 8; ++gi) sum += red[gi * NV + lane];
       const int l = lane / 10, q = lane - (lane / 10) * 10;
       float* part = a.partials + d.partial_begin;
-      as_global(part)[((int64_t)(pair * LV + l) * d.n_witems + witem) * 10 + q] = tot;
+      as_global(part)[((int64_t)(pair * LV + l) * d.n_witems + witem) * 10 + q] = sum;
     }
   }
 }
@@ -422,14 +474,9 @@ __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a) {
 #define TC_LAUNCHER_X(dt, lv) TC_LAUNCHER(dt, lv)
 
 hipError_t TC_LAUNCHER_X(TC_FUSED_DT, TC_FUSED_LV)(const FusedLaunch& f, hipStream_t s) {
+  if (f.band_rows < 16 || f.band_rows > 256 || f.band_rows % 16 != 0) return hipErrorInvalidValue;
   const FusedArgs a = make_args(f);
-  const dim3 grid((unsigned)f.grid), block(64);
-  switch (f.band_rows) {
-    case 8: hipLaunchKernelGGL(ttc_fused<8>, grid, block, 0, s, a); break;
-    case 16: hipLaunchKernelGGL(ttc_fused<16>, grid, block, 0, s, a); break;
-    case 32: hipLaunchKernelGGL(ttc_fused<32>, grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(ttc_fused, dim3((unsigned)f.grid), dim3(64), 0, s, a, f.band_rows);
   return hipGetLastError();
 }
 

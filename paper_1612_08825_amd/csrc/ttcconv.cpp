@@ -634,11 +634,15 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // The tuning sweep's best launch shape per frame type and level count on
 // MI355X (f16: the 64-stream batched workload; u8: a 64-stream serving mix).
 tc_ttc_tuning default_tuning(int dtype, int levels) {
-  static const tc_ttc_tuning f16[TC_MAX_LEVELS] = {{32, 128}, {32, 16}, {32, 16}, {32, 128}};
-  static const tc_ttc_tuning u8[TC_MAX_LEVELS] = {{16, 32}, {32, 16}, {32, 16}, {32, 16}};
+  static const tc_ttc_tuning f16[TC_MAX_LEVELS] = {{128, 128}, {128, 64}, {128, 128}, {128, 128}};
+  static const tc_ttc_tuning u8[TC_MAX_LEVELS] = {{64, 128}, {64, 128}, {64, 128}, {128, 64}};
   const int l = levels < 1 ? 0 : (levels > TC_MAX_LEVELS ? TC_MAX_LEVELS - 1 : levels - 1);
   return dtype == TC_U8 ? u8[l] : f16[l];
 }
+
+// One frame pair per call (tc_ttc_solve): the shortest band, so that a single
+// pair still spreads over many waves.
+constexpr tc_ttc_tuning kPairTuning = {16, 32};
 
 bool tuning_ok(const tc_ttc_tuning& t, int dtype, int levels) {
   return t.groups_per_cu >= 1 && t.groups_per_cu <= 256 && fused_variant_exists(dtype, levels, t.band_rows);
@@ -885,7 +889,7 @@ int pair_desc(const tc_tensor* prev, const tc_tensor* next, int32_t levels, SeqD
   q.n_frames = 2;
   q.levels = levels;
   if ((st = validate_seq(q, prev->dtype, levels)) != TC_OK) return st;
-  fill_desc(d, q, prev->dtype, default_tuning(prev->dtype, levels).band_rows);
+  fill_desc(d, q, prev->dtype, kPairTuning.band_rows);
   d.item_begin = 0;
   d.pair_begin = 0;
   d.partial_begin = 0;
@@ -908,7 +912,7 @@ extern "C" int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_
     q.n_frames = 2;
     q.levels = levels;
     SeqDesc d{};
-    fill_desc(d, q, dt, 8);  // the smallest band height has the most partials
+    fill_desc(d, q, dt, 16);  // the smallest band height has the most partials
     best = std::max(best, pair_ws_bytes(d));
   }
   *ws_bytes = best;
@@ -1029,7 +1033,7 @@ extern "C" int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_
   f.n_items = d.n_witems;
   f.n_pairs = 1;
   f.partials = reinterpret_cast<float*>(ws);
-  f.grid = persistent_grid(f.n_items, default_tuning(prev->dtype, levels).groups_per_cu);
+  f.grid = persistent_grid(f.n_items, kPairTuning.groups_per_cu);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (launch_ttc_fused(f, s) != hipSuccess) return TC_EDEVICE;
   if (launch_ttc_finish(f, levels_out, pick_out, s) != hipSuccess) return TC_EDEVICE;

@@ -322,8 +322,12 @@ class GpuExecutor:
     ``host_frames[sid]`` is a pinned [F, H, W] u8 tensor; request ``k`` of
     stream ``sid`` carries frame ``k % F`` of it."""
 
+    # A tick carries few pairs: short bands spread each pair over many waves
+    # (the library's built-in launch shape is chosen for large batches).
+    LATENCY_TUNING = (16, 32)
+
     def __init__(self, host_frames: Sequence, levels: int = 3, ring: int = 3, max_inflight: int = 2,
-                 tuning=None, device=None):
+                 tuning=LATENCY_TUNING, device=None):
         import torch
 
         from . import api

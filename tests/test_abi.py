@@ -236,15 +236,15 @@ def test_ttc_plan_validation(lib):
 def test_ttc_tuning_defaults_and_rejections(lib):
     t = L.TcTuning()
     # the sweep's choices, per frame type and level count
-    want = {(L.TC_F16, 4): (32, 128), (L.TC_F16, 3): (32, 16), (L.TC_F16, 1): (32, 128), (L.TC_U8, 3): (32, 16),
-            (L.TC_U8, 1): (16, 32)}
+    want = {(L.TC_F16, 4): (128, 128), (L.TC_F16, 2): (128, 64), (L.TC_F16, 1): (128, 128), (L.TC_U8, 3): (64, 128),
+            (L.TC_U8, 4): (128, 64)}
     for (dt, lv), shape in want.items():
         assert lib.tc_ttc_tuning_default(dt, lv, C.byref(t)) == 0
         assert (t.band_rows, t.groups_per_cu) == shape, (dt, lv)
     assert lib.tc_ttc_tuning_default(L.TC_F32, 3, C.byref(t)) == L.TC_EDTYPE
     h = C.c_void_p()
     arr = (L.TcSeq * 1)(_seq(64, 64, levels=3))
-    for rows, gpc in [(12, 32), (8, 0), (8, 257), (64, 32), (0, 8)]:
+    for rows, gpc in [(12, 32), (8, 32), (24, 32), (272, 32), (16, 0), (16, 257), (0, 8)]:
         t.band_rows, t.groups_per_cu = rows, gpc
         assert lib.tc_ttc_plan_create_ex(arr, 1, L.TC_U8, C.byref(t), C.byref(h)) == L.TC_EINVAL, (rows, gpc)
         assert not h.value

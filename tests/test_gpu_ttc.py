@@ -162,7 +162,12 @@ def test_every_tuning_candidate(api, dtype, levels):
     """Work-groups per CU never change a result (bitwise); every band height
     stays within the oracle tolerance."""
     specs, vids = _small_batch(dtype, 9)
-    for rows in (8, 16, 32):
+    # and one stream tall enough for several full bands at every height (the
+    # unchecked walk with its inner loop) besides the bottom band
+    tall = synth.stream_specs(4, 1, 3, dtype, sizes=[(700, 300)], case=10)
+    specs = list(specs) + tall
+    vids = list(vids) + [torch.from_numpy(np.ascontiguousarray(tall[0].render())).cuda()]
+    for rows in (16, 32, 64, 128):
         ref = None
         for gpc in (1, 8, 64, 256):
             recs, picks = api.ttc_solve_batched(vids, levels, tuning=(rows, gpc))

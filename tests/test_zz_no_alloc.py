@@ -52,17 +52,24 @@ def test_noalloc_equals_workspace_entry_point(api, dtype):
 def test_noalloc_rejects_beyond_scratch(api):
     from paper_1612_08825_amd import _lib as L
 
+    lib = api._lib()
+    side, levels = 60000, 4
+    # the descriptors below claim a frame far larger than the buffer behind
+    # them; that is safe only because the entry point refuses the pair on the
+    # host, before any launch.  Make sure of that first, on the host: the
+    # pair's workspace must exceed the scratch array.
+    n = C.c_size_t(0)
+    assert lib.tc_ttc_workspace_size(side, side, levels, C.byref(n)) == L.TC_OK
+    assert n.value > 4 * L.TC_NOALLOC_SCRATCH_BYTES, n.value
     buf = torch.zeros((2, 64, 64), dtype=torch.uint8, device="cuda")
     d0, d1 = api._desc(buf[0]), api._desc(buf[1])
-    # describe a 12000 x 12000 pair: its partials exceed the scratch array, so
-    # the call returns before it touches (or launches anything over) the memory
     for d in (d0, d1):
-        d.shape[0] = d.shape[1] = 12000
-        d.stride[0] = 12000
-    lv = torch.zeros(4 * L.LEVEL_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+        d.shape[0] = d.shape[1] = side
+        d.stride[0] = side
+    lv = torch.zeros(levels * L.LEVEL_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
     pk = torch.zeros(L.PICK_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
-    rc = api._lib().tc_ttc_solve_noalloc(C.byref(d0), C.byref(d1), 4, C.c_void_p(lv.data_ptr()),
-                                         C.c_void_p(pk.data_ptr()), api._stream())
+    rc = lib.tc_ttc_solve_noalloc(C.byref(d0), C.byref(d1), levels, C.c_void_p(lv.data_ptr()),
+                                  C.c_void_p(pk.data_ptr()), api._stream())
     assert rc == L.TC_ENOMEM
     torch.cuda.synchronize()
     assert int(lv.sum()) == 0 and int(pk.sum()) == 0

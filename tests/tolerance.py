@@ -6,14 +6,15 @@ Convolution (FP32 accumulation of K products per output, any order):
     target read against the sum of absolute products, since an element-wise
     relative error is meaningless where y ~ 0.
 
-TTC sums: the GPU forms FP32 products, sums at most BLOCK terms per lane in
-plain FP32, reduces the 64 lanes of a wave in REDUCE_DEPTH rounded additions
-(three DPP steps within groups of 8 lanes, then the 8 group totals added in
-sequence), and combines the waves with TwoSum in the finishing pass.  The
-error of every sum is therefore bounded by
+TTC sums: the GPU forms FP32 products and sums them per lane in plain FP32
+register blocks of at most BLOCK terms (16 rows x 8 columns at level 0), adds
+the block totals of a band in FP32 (at most BLOCKS of them: 256 / 16 + 1 for
+the tallest band the tuning allows), reduces the 64 lanes of a wave in
+REDUCE_DEPTH rounded additions (three DPP steps within groups of 8 lanes, then
+the 8 group totals added in sequence), and combines the bands with TwoSum in
+the finishing pass.  The error of every sum is therefore bounded by
     |s - s64| <= TAU_SUM * sum|terms|,
-TAU_SUM = (BLOCK + REDUCE_DEPTH + 8) * 2^-24 with BLOCK = 8 * 32 cubes per lane
-(the tallest band the tuning allows times eight columns); the 8 covers the
+TAU_SUM = (BLOCK + BLOCKS + REDUCE_DEPTH + 8) * 2^-24; the 8 covers the
 rounding of the products and of G.  The bound on A, B, C follows from first-order perturbation
 of the normal equations, dv = -M^-1 (dM v + dr), with every sum moved by its
 own bound in the worst direction; TTC and FOE follow from C and (A, B).
@@ -34,9 +35,10 @@ import numpy as np
 import oracle as O
 
 TAU_CONV = 1e-5
-BLOCK = 8 * 32
+BLOCK = 16 * 8
+BLOCKS = 256 // 16 + 1
 REDUCE_DEPTH = 3 + 7
-TAU_SUM = (BLOCK + REDUCE_DEPTH + 8) * 2.0 ** -24
+TAU_SUM = (BLOCK + BLOCKS + REDUCE_DEPTH + 8) * 2.0 ** -24
 
 
 def abs_sums(P0, P1, level, H0, W0):
