@@ -23,6 +23,8 @@ SOURCES = ["conv.hip", "fft.hip", "pyramid.hip", "ttc.hip", "ttc_variant.hip", "
 # the fused pass is built once per frame type (0 = u8, 1 = f16) and level count
 FUSED = [("ttc_fused.hip", f"ttc_fused_dt{dt}_l{lv}", [f"-DTC_FUSED_DT={dt}", f"-DTC_FUSED_LV={lv}"])
          for dt in (1, 0) for lv in (4, 3, 2, 1)]
+# the row-streaming convolution is built once per input type (0 f32, 1 f16, 2 u8)
+ROWS = [("conv_rows.hip", f"conv_rows_dt{dt}", [f"-DTC_ROWS_DT={dt}"]) for dt in (0, 1, 2)]
 
 ARCH = "gfx950"
 COMMON = [
@@ -65,7 +67,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     jobs = jobs or min(16, os.cpu_count() or 4)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
         # the slowest objects (the fused pass) first
-        objs = list(ex.map(lambda s: _compile(s, verbose), FUSED + SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose), FUSED + ROWS + SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

@@ -18,11 +18,14 @@
 // row last to first; conv2d_rows visits tap rows from last to first.
 #include <type_traits>
 
+#include "conv_common.hpp"
 #include "device_common.hpp"
 #include "internal.hpp"
 
 namespace ttc {
 namespace {
+
+using namespace rows;
 
 constexpr int kTX = 16, kTY = 16;   // threads per work-group (x, y)
 constexpr int kRX = 4, kRY = 4;     // outputs per thread (x, y)
@@ -266,182 +269,6 @@ hipError_t launch_tiled(int xdt, const Tile2D& t, int kwmax, dim3 grid, hipStrea
 // column at a time with buffer loads through a resource limited to the row,
 // which read zero left and right of the image; bands whose rows may leave the
 // image skip those rows.
-typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
-template <typename T> using cptr = __attribute__((address_space(4))) const T*;
-
-template <int KW, int S> constexpr int row_chunks() { return (S + KW + 3 + 3) / 4; }
-template <int KW, int S> constexpr int row_lanes_out() { return 65 - row_chunks<KW, S>(); }
-
-struct RowArgs {
-  const float* x;
-  int64_t xs0, xsd;  // row and plane strides (elements)
-  int H, W, D;
-  const float* k;    // contiguous [KD][KH][KW]
-  int KD;
-  float* y;
-  int64_t ys0, ysd;
-  int OH, OW, OD;
-  int off0, off1, offd;
-  int n_bands, n_cw;
-  int64_t n_items;   // OD * n_bands * n_cw
-};
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
-}
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int cmin(int a, int b) { return a < b ? a : b; }
-
-// Buffer resource over `bytes` bytes from `base` (gfx9 raw-buffer word 3:
-// 32-bit data format, no swizzle).  A buffer load whose offset is outside the
-// range returns zero without touching memory (on this chip the scalar offset
-// counts toward the range too).  So with the row start as base, W * 4 bytes as
-// range and the column (times 4, as an unsigned 32-bit lane value) as the
-// vector offset, every load of a column left or right of the image reads zero.
-// (Multi-dword buffer loads are not used: they need aligned offsets.)
-constexpr int kBufWord3 = 0x00020000;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufWord3);
-}
-
-// Value of lane i + 1 (DPP wave_shl:1, whole wave); lane 63 receives 0.
-__device__ __forceinline__ float from_next_lane(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xF, 0xF, true));
-}
-
-// acc[j][c] += sum over taps of one kernel plane, for the band's input rows
-// i0 .. i0 + R + KH - 2 (output row j of the band takes input rows
-// i0 + j .. i0 + j + KH - 1 with tap rows KH - 1 .. 0).  EDGE: some lane's
-// chunk may reach outside the image (such a lane loads its chunk one
-// range-checked column at a time); ROWCHECK: input rows may lie outside the
-// image (uniform across the wave; they are skipped).
-template <int KH, int KW, int R, int S, bool EDGE, bool ROWCHECK>
-__device__ __forceinline__ void band_accumulate(float (&acc)[R][4], const float* plane, uint32_t row_bytes,
-                                                int chunk0, uint32_t lane_col, int64_t xs0, int H, int i0,
-                                                cptr<float> taps) {
-  constexpr int NW = KW + 3;
-  constexpr int NC = row_chunks<KW, S>();
-  static_for<0, R + KH - 1>([&](auto tc) {
-    constexpr int t = decltype(tc)::value;
-    const int row = i0 + t;
-    if (!ROWCHECK || (row >= 0 && row < H)) {
-      const float* rp = plane + (int64_t)row * xs0;
-      // this lane's chunk, then those of the next NC - 1 lanes
-      float ch[4 * NC];
-      const int cc = chunk0 + (int)lane_col;  // first column of the chunk
-      const int W = (int)(row_bytes >> 2);
-      if (!EDGE || (cc >= 0 && cc + 4 <= W)) {
-        const f4u v = *(const __attribute__((address_space(1))) f4u*)(rp + cc);
-        ch[0] = v.x;
-        ch[1] = v.y;
-        ch[2] = v.z;
-        ch[3] = v.w;
-      } else if (cc >= W || cc + 4 <= 0) {
-        ch[0] = ch[1] = ch[2] = ch[3] = 0.f;  // wholly outside: no load
-      } else {
-        // a chunk reaching outside the image: one range-checked load per column
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(rp, row_bytes);
-#pragma unroll
-        for (int d = 0; d < 4; ++d)
-          ch[d] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)(cc + d) * 4u, 0, 0));
-      }
-#pragma unroll
-      for (int k = 1; k < NC; ++k)
-#pragma unroll
-        for (int d = 0; d < 4; ++d) ch[4 * k + d] = from_next_lane(ch[4 * (k - 1) + d]);
-      float w[NW];
-#pragma unroll
-      for (int e = 0; e < NW; ++e) w[e] = ch[S + e];
-      static_for<cmax(0, t - KH + 1), cmin(R - 1, t) + 1>([&](auto jc) {
-        constexpr int j = decltype(jc)::value;
-        constexpr int a = j + KH - 1 - t;  // tap row
-#pragma unroll
-        for (int b = 0; b < KW; ++b) {
-          const float kv = taps[a * KW + b];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[j][c] = fmaf(kv, w[c + KW - 1 - b], acc[j][c]);
-        }
-      });
-    }
-  });
-}
-
-// At least WPE waves per SIMD (<= 512 / WPE VGPRs): left alone, the compiler
-// issues every row load of the unrolled band up front and holds them all.
-template <int KH, int KW, int R, int S, int WPE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void conv2d_rows(RowArgs a) {
-  constexpr int LO = row_lanes_out<KW, S>();
-  const int lane = threadIdx.x;
-  const int64_t G = gridDim.x, g = blockIdx.x;
-  // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin; give each
-  // XCD a contiguous run of items, so vertically adjacent bands (which share
-  // KH - 1 input rows) meet in the same L2.  Items run across a band's column
-  // strips first, so that concurrent waves read whole row segments.
-  const int64_t item = (G % 8 == 0) ? (g % 8) * (G / 8) + g / 8 : g;
-  if (item >= a.n_items) return;
-  const int64_t per_plane = (int64_t)a.n_bands * a.n_cw;
-  const int od = (int)(item / per_plane);
-  const int rem = (int)(item - (int64_t)od * per_plane);
-  const int band = rem / a.n_cw;
-  const int cw = rem - band * a.n_cw;
-  const int o0 = band * R;
-  const int p_wave = cw * 4 * LO;
-  const int p_lane = p_wave + 4 * lane;
-  // first column of lane 0's chunk: lane i's window starts S columns into its
-  // chunk, at full column p_lane + off1 - (KW - 1)
-  const int chunk0 = p_wave + a.off1 - (KW - 1) - S;
-  const uint32_t lane_col = 4u * (uint32_t)lane;
-  const int i0 = o0 + a.off0 - (KH - 1);  // first input row of the band
-  const bool rows_in = i0 >= 0 && i0 + R + KH - 2 < a.H;
-  const bool cols_in = chunk0 >= 0 && chunk0 + 256 <= a.W;
-
-  float acc[R][4];
-#pragma unroll
-  for (int j = 0; j < R; ++j)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[j][c] = 0.f;
-
-  const int nd = od + a.offd;  // full-result plane
-  for (int kd = 0; kd < a.KD; ++kd) {
-    const int xd = nd - kd;
-    if (xd < 0 || xd >= a.D) continue;  // uniform
-    const float* plane = a.x + (int64_t)xd * a.xsd;
-    const uint32_t row_bytes = (uint32_t)a.W * 4u;
-    const cptr<float> taps = (cptr<float>)(a.k) + kd * KH * KW;
-    if (rows_in && cols_in)
-      band_accumulate<KH, KW, R, S, false, false>(acc, plane, row_bytes, chunk0, lane_col, a.xs0, a.H, i0, taps);
-    else if (cols_in)
-      band_accumulate<KH, KW, R, S, false, true>(acc, plane, row_bytes, chunk0, lane_col, a.xs0, a.H, i0, taps);
-    else
-      band_accumulate<KH, KW, R, S, true, true>(acc, plane, row_bytes, chunk0, lane_col, a.xs0, a.H, i0, taps);
-  }
-
-  if (lane >= LO) return;
-  const gptr<float> yp = as_global(a.y) + (int64_t)od * a.ysd;
-#pragma unroll
-  for (int j = 0; j < R; ++j) {
-    const int o = o0 + j;
-    if (o >= a.OH) break;
-    const gptr<float> yr = yp + (int64_t)o * a.ys0 + p_lane;
-    if (p_lane + 3 < a.OW) {
-      f4u v;
-      v.x = acc[j][0];
-      v.y = acc[j][1];
-      v.z = acc[j][2];
-      v.w = acc[j][3];
-      *(__attribute__((address_space(1))) f4u*)yr = v;
-    } else {
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-        if (p_lane + c < a.OW) yr[c] = acc[j][c];
-    }
-  }
-}
-
 // Large square kernels (15 x 15): the unrolled band of conv2d_rows would need
 // all KH * KW taps live in scalar registers at once.  Here the band's input
 // rows are a runtime loop with a rolling window of KH accumulator rows: at
@@ -477,12 +304,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void co
   const int i0 = o0 + a.off0 - (KH - 1);
   const int n_out = RB < a.OH - o0 ? RB : a.OH - o0;  // band rows inside the output
   const int n_rows = n_out + KH - 1;
-  const gptr<float> yp = as_global(a.y) + (int64_t)od * a.ysd;
+  const gptr<float> yp = as_global(static_cast<float*>(a.y)) + (int64_t)od * a.ysd;
   const bool store_lane = lane < LO;
 
   // only one kernel plane per output plane is supported here (2-D)
-  const float* plane = a.x;
-  cptr<float> taps = (cptr<float>)(a.k);
+  const float* plane = static_cast<const float*>(a.x);
+  cptr<float> taps = (cptr<float>)(static_cast<const float*>(a.k));
 
   auto load_chunk = [&](int row, float (&c4)[4]) {
     if (row < 0 || row >= a.H) {  // uniform
@@ -618,7 +445,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void co
   const int i0 = o0 + a.off0 - (K - 1);
   const int n_out = RB < a.OH - o0 ? RB : a.OH - o0;
   const int n_rows = n_out + K - 1;
-  const gptr<float> yp = as_global(a.y);
+  const gptr<float> yp = as_global(static_cast<float*>(a.y));
   const bool store_lane = lane < LO;
   const cptr<float> u = (cptr<float>)tp.u;
   const cptr<float> v = (cptr<float>)tp.v;
@@ -628,7 +455,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void co
       c4[0] = c4[1] = c4[2] = c4[3] = 0.f;
       return;
     }
-    const float* rp = a.x + (int64_t)row * a.xs0;
+    const float* rp = static_cast<const float*>(a.x) + (int64_t)row * a.xs0;
     if (chunk_in) {
       const f4u q = *(const __attribute__((address_space(1))) f4u*)(rp + cc);
       c4[0] = q.x;
@@ -735,32 +562,12 @@ hipError_t launch_sep_k(const RowArgs& ra, const SepTaps& tp, hipStream_t s) {
   return launch_sep_rb<K, 8>(ra, tp, s);
 }
 
-template <int KH, int KW, int R, int S>
-hipError_t launch_rows_s(RowArgs ra, hipStream_t s) {
-  constexpr int LO = row_lanes_out<KW, S>();
-  ra.n_bands = (ra.OH + R - 1) / R;
-  ra.n_cw = (ra.OW + 4 * LO - 1) / (4 * LO);
-  ra.n_items = (int64_t)ra.OD * ra.n_bands * ra.n_cw;
-  const int64_t grid = (ra.n_items + 7) / 8 * 8;
-  hipLaunchKernelGGL((conv2d_rows<KH, KW, R, S, 4>), dim3((unsigned)grid), dim3(64), 0, s, ra);
-  return hipGetLastError();
-}
-
-template <int KH, int KW, int R>
-hipError_t launch_rows_t(const RowArgs& ra, hipStream_t s) {
-  // the window's offset inside a chunk: (off1 - (KW - 1)) mod 4
-  switch ((((ra.off1 - (KW - 1)) % 4) + 4) % 4) {
-    case 0: return launch_rows_s<KH, KW, R, 0>(ra, s);
-    case 1: return launch_rows_s<KH, KW, R, 1>(ra, s);
-    case 2: return launch_rows_s<KH, KW, R, 2>(ra, s);
-    default: return launch_rows_s<KH, KW, R, 3>(ra, s);
-  }
-}
-
 // The (KH, KW) pairs the row-streaming kernels are built for (15 x 15 only
-// for 2-D: the rolling kernel takes one kernel plane).
-bool rows_variant(int KH, int KW, int rank) {
-  return KH == KW && (KH == 2 || KH == 3 || KH == 5 || KH == 7 || (KH == 15 && rank == 2));
+// for 2-D FP32: the rolling kernel takes one kernel plane).
+bool rows_variant(int KH, int KW, int rank, int xdt) {
+  if (KH != KW) return false;
+  if (KH == 2 || KH == 3 || KH == 5 || KH == 7) return true;
+  return KH == 15 && rank == 2 && xdt == TC_F32;
 }
 
 // Items (waves) a band height gives; the band height is the tallest that still
@@ -770,18 +577,16 @@ int64_t row_items(const RowArgs& ra, int rb, int lanes_out) {
 }
 constexpr int64_t kTargetItems = 2048;
 
-hipError_t launch_rows(const RowArgs& ra, int KH, hipStream_t s) {
+hipError_t launch_rows(const RowArgs& ra, int KH, int xdt, hipStream_t s) {
   if (KH == 15) {
     if (row_items(ra, 32, 59) >= kTargetItems) return launch_roll_t<15, 15, 32>(ra, s);
     if (row_items(ra, 16, 59) >= kTargetItems) return launch_roll_t<15, 15, 16>(ra, s);
     return launch_roll_t<15, 15, 8>(ra, s);
   }
-  const bool small = row_items(ra, 8, 61) < kTargetItems;
-  switch (KH) {
-    case 2: return small ? launch_rows_t<2, 2, 4>(ra, s) : launch_rows_t<2, 2, 8>(ra, s);
-    case 3: return small ? launch_rows_t<3, 3, 4>(ra, s) : launch_rows_t<3, 3, 8>(ra, s);
-    case 5: return small ? launch_rows_t<5, 5, 4>(ra, s) : launch_rows_t<5, 5, 8>(ra, s);
-    case 7: return small ? launch_rows_t<7, 7, 4>(ra, s) : launch_rows_t<7, 7, 8>(ra, s);
+  switch (xdt) {
+    case TC_F32: return launch_rows_dt0(ra, KH, s);
+    case TC_F16: return launch_rows_dt1(ra, KH, s);
+    case TC_U8: return launch_rows_dt2(ra, KH, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -839,21 +644,27 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
   if (n_out == 0) return hipSuccess;
 
   const int r = c.ndim;
-  // 2-D and 3-D FP32 with contiguous rows and a common kernel size: the
-  // row-streaming kernel.
-  if ((r == 2 || r == 3) && c.xdt == TC_F32 && c.xstride[r - 1] == 1 && c.ystride[r - 1] == 1 &&
-      rows_variant((int)c.kshape[r - 2], (int)c.kshape[r - 1], r) && c.xshape[r - 1] < (1LL << 28) &&
+  // 2-D and 3-D images with contiguous rows and a common kernel size: the
+  // row-streaming kernels (FP32; FP16 and u8 when each row's 4-pixel chunks
+  // start on 4-byte boundaries; u8 with 24-bit taps only).
+  const int es = c.xdt == TC_F32 ? 4 : (c.xdt == TC_F16 ? 2 : 1);
+  const bool chunks_aligned = (reinterpret_cast<uintptr_t>(c.x) % 4 == 0) && ((c.xstride[r - 2] * es) % 4 == 0) &&
+                              (r == 2 || (c.xstride[0] * es) % 4 == 0);
+  const bool rows_type_ok = c.xdt == TC_F32 || (c.xdt == TC_F16 && chunks_aligned) ||
+                            (c.xdt == TC_U8 && chunks_aligned && small_taps);
+  if ((r == 2 || r == 3) && rows_type_ok && c.xstride[r - 1] == 1 && c.ystride[r - 1] == 1 &&
+      rows_variant((int)c.kshape[r - 2], (int)c.kshape[r - 1], r, c.xdt) && c.xshape[r - 1] < (1LL << 28) &&
       c.xshape[r - 2] < (1LL << 30) && c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&
       c.off[r - 1] < (1LL << 30) && c.off[r - 2] < (1LL << 30) &&
       (r == 2 || (c.xshape[0] < (1LL << 30) && c.yshape[0] < (1LL << 20) && c.kshape[0] < (1LL << 20) &&
                   c.off[0] < (1LL << 30)))) {
     RowArgs ra{};
-    ra.x = static_cast<const float*>(c.x);
+    ra.x = c.x;
     ra.xs0 = c.xstride[r - 2];
     ra.H = (int)c.xshape[r - 2];
     ra.W = (int)c.xshape[r - 1];
-    ra.k = static_cast<const float*>(c.k);
-    ra.y = static_cast<float*>(c.y);
+    ra.k = c.k;
+    ra.y = c.y;
     ra.ys0 = c.ystride[r - 2];
     ra.OH = (int)c.yshape[r - 2];
     ra.OW = (int)c.yshape[r - 1];
@@ -874,7 +685,7 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
       ra.OD = 1;
       ra.offd = 0;
     }
-    return launch_rows(ra, (int)c.kshape[r - 2], s);
+    return launch_rows(ra, (int)c.kshape[r - 2], c.xdt, s);
   }
 
   // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 48

@@ -235,3 +235,87 @@ def test_conv_separable_rejects(api):
     u5 = torch.zeros(5, dtype=torch.float32, device="cuda")
     with pytest.raises(L.TTCError):
         api.conv_nd_separable(x.t(), u5, u5, "full")      # rows not contiguous
+
+
+# ----------------------------------------------------------------------------- row kernels for u8 and f16 images
+ROW_SHAPES = [((70, 130), (3, 3)), ((61, 777), (3, 3)), ((45, 601), (2, 2)), ((37, 530), (5, 5)), ((29, 1101), (7, 7)),
+              ((9, 300), (7, 7)), ((3, 5), (5, 5)), ((130, 255), (3, 3))]
+
+
+@pytest.mark.parametrize("xs,ks", ROW_SHAPES)
+@pytest.mark.parametrize("mode", ["full", "same", "valid"])
+def test_conv2d_rows_u8_exact(api, xs, ks, mode):
+    """u8 (*) int32 through the row-streaming kernel: bit-exact."""
+    try:
+        O.conv_out_shape(xs, ks, mode)
+    except ValueError:
+        pytest.skip("mixed extents are rejected in valid mode")
+    x = synth.conv_image(xs, case=31, dtype="u8")
+    k = synth.conv_kernel(ks, case=31, dtype="i32", int_range=100)
+    y = api.conv_nd_ex(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode, method="direct",
+                       k_host=k).cpu().numpy()
+    np.testing.assert_array_equal(y.astype(np.int64), O.conv(x, k, mode))
+
+
+@pytest.mark.parametrize("xs,ks", ROW_SHAPES)
+@pytest.mark.parametrize("mode", ["full", "same", "valid"])
+def test_conv2d_rows_f16(api, xs, ks, mode):
+    try:
+        O.conv_out_shape(xs, ks, mode)
+    except ValueError:
+        pytest.skip("mixed extents are rejected in valid mode")
+    x = synth.conv_image(xs, case=32, dtype="f16")
+    k = synth.conv_kernel(ks, case=32)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+    _check_float(y, x, k, mode, f"f16 rows {xs}*{ks} {mode}")
+
+
+def test_conv_rows_unaligned_views(api):
+    """u8 and f16 views whose rows do not start on 4-byte boundaries take the
+    tiled kernels; results are the same definition."""
+    xu = synth.conv_image((40, 203), case=33, dtype="u8")
+    ku = synth.conv_kernel((3, 3), case=33, dtype="i32")
+    base = torch.from_numpy(xu).cuda()
+    v = base[:, 1:]  # row starts at an odd byte
+    y = api.conv_nd_ex(v, torch.from_numpy(ku).cuda(), "full", k_host=ku).cpu().numpy()
+    np.testing.assert_array_equal(y.astype(np.int64), O.conv(xu[:, 1:], ku, "full"))
+    xh = synth.conv_image((40, 203), case=34, dtype="f16")
+    kh = synth.conv_kernel((5, 5), case=34)
+    vh = torch.from_numpy(xh).cuda()[:, 1:]
+    yh = api.conv_nd(vh, torch.from_numpy(kh).cuda(), "same").cpu().numpy()
+    _check_float(yh, xh[:, 1:], kh, "same", "f16 unaligned")
+
+
+@pytest.mark.parametrize("dtype,K", [("u8", 3), ("u8", 7), ("f16", 3), ("f16", 7)])
+def test_conv_rows_benchmark_sizes_sampled(api, dtype, K):
+    x = synth.conv_image((4096, 4096), case=500 + K, dtype=dtype)
+    if dtype == "u8":
+        k = synth.conv_kernel((K, K), case=500 + K, dtype="i32")
+        y = api.conv_nd_ex(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), "full", k_host=k)
+    else:
+        k = synth.conv_kernel((K, K), case=500 + K)
+        y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), "full")
+    rng = np.random.default_rng(K)
+    idx = _sample_index(tuple(y.shape), 600, rng)
+    got = y.cpu().numpy()[tuple(np.array(idx).T)]
+    ref = O.conv_at(x, k, "full", idx)
+    if dtype == "u8":
+        np.testing.assert_array_equal(got.astype(np.int64), ref)
+    else:
+        bound = TAU_CONV * O.conv_at(np.abs(x.astype(np.float64)), np.abs(k.astype(np.float64)), "full", idx)
+        assert np.all(np.abs(got - ref) <= bound)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f16"])
+def test_conv3d_rows_u8_f16(api, dtype):
+    xs, ks = (6, 40, 260), (3, 3, 3)
+    x = synth.conv_image(xs, case=35, dtype=dtype)
+    for mode in ("full", "same", "valid"):
+        if dtype == "u8":
+            k = synth.conv_kernel(ks, case=35, dtype="i32")
+            y = api.conv_nd_ex(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode, k_host=k).cpu().numpy()
+            np.testing.assert_array_equal(y.astype(np.int64), O.conv(x, k, mode))
+        else:
+            k = synth.conv_kernel(ks, case=35)
+            y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+            _check_float(y, x, k, mode, f"f16 3d {mode}")
