@@ -265,8 +265,6 @@ def conv_sweep(api, torch, steps, use_graph=True):
         es = x0.element_size()
         nbytes = es * math.prod(xs) + 4 * math.prod(ys)
         ydt = torch.int32 if kind == "u8" else torch.float32
-        ys = tuple(a + b - 1 for a, b in zip(xs, ks))
-        nbytes = 4 * (math.prod(xs) + math.prod(ys))
         nbuf = max(2, min(64, int(math.ceil(1.1 * 2 ** 30 / nbytes))))
         xbufs = [x0.clone() for _ in range(nbuf)]
         ybufs = [torch.empty(ys, dtype=ydt, device="cuda") for _ in range(nbuf)]

@@ -28,7 +28,11 @@
 // column at a time with buffer loads through a resource limited to the row,
 // which read zero left and right of the image; bands whose rows may leave the
 // image skip those rows.  For rank 3 the item is one output plane and the
-// kernel planes are walked in turn, each over its input plane.
+// kernel planes are walked in turn, each over its input plane -- except for
+// 3 x 3 x 3 kernels over images whose rows are a multiple of 4 wide, which
+// take conv3d_rows: runs of output planes, each input plane loaded once, and
+// waves split into lane groups so that rows just over one wave wide waste
+// fewer lanes.
 #include "conv_common.hpp"
 
 #if !defined(TC_ROWS_DT)
@@ -56,6 +60,18 @@ template <> struct Io<0> {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)col * 4u, 0, 0));
   }
   __device__ static TA mac(TA acc, TA k, TA v) { return fmaf(k, v, acc); }
+  __device__ static TA mul(TA k, TA v) { return k * v; }
+  // the chunk at byte offset off of a buffer (zero where out of range)
+  __device__ static void chunk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, TA (&c4)[4]) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+    // element by element through a scalar: a bit_cast of a vector element
+    // expression would read element 0 whatever the index
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t u = v[d];
+      c4[d] = __builtin_bit_cast(float, u);
+    }
+  }
 };
 
 // FP16: one 8-byte load per chunk, exact conversion to FP32
@@ -78,6 +94,14 @@ template <> struct Io<1> {
     return (float)__builtin_bit_cast(_Float16, h);
   }
   __device__ static TA mac(TA acc, TA k, TA v) { return fmaf(k, v, acc); }
+  __device__ static TA mul(TA k, TA v) { return k * v; }
+  __device__ static void chunk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, TA (&c4)[4]) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    c4[0] = half(v[0], 0);
+    c4[1] = half(v[0], 1);
+    c4[2] = half(v[1], 0);
+    c4[3] = half(v[1], 1);
+  }
 };
 
 // u8: one 4-byte load per chunk; taps below 2^23 in magnitude times pixels
@@ -96,6 +120,14 @@ template <> struct Io<2> {
     return (int)__builtin_amdgcn_raw_buffer_load_b8(rs, (uint32_t)col, 0, 0);
   }
   __device__ static TA mac(TA acc, TA k, TA v) { return acc + __mul24(k, v); }
+  __device__ static TA mul(TA k, TA v) { return __mul24(k, v); }
+  __device__ static void chunk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, TA (&c4)[4]) {
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    c4[0] = (int)(v & 0xffu);
+    c4[1] = (int)((v >> 8) & 0xffu);
+    c4[2] = (int)((v >> 16) & 0xffu);
+    c4[3] = (int)(v >> 24);
+  }
 };
 
 using IO = Io<TC_ROWS_DT>;
@@ -229,6 +261,266 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   }
 }
 
+// The NR rows of one input plane that a band reads, one chunk per lane and
+// row, through a buffer resource over the plane: off[t] is the chunk's byte
+// offset in the plane, or kOutside for a row or chunk outside the image,
+// which the buffer's range check reads as zero.  Loads only: the products
+// come after the caller's stores.
+constexpr uint32_t kOutside = 0x80000000u;  // beyond any plane taken here (< 2 GiB)
+template <int NR>
+__device__ __forceinline__ void load_band(TA (&rows)[NR][4], __amdgpu_buffer_rsrc_t plane, const uint32_t (&off)[NR]) {
+  static_for<0, NR>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    IO::chunk_buf(plane, off[t], rows[t]);
+  });
+}
+
+// acc[slot(kd)][j][c] += the band's input rows (one input plane) x taps of
+// kernel plane kd, for the kernel planes kd_lo .. kd_hi (those whose output
+// planes belong to the run; uniform): each row feeds every output plane it
+// contributes to.  The slot of kernel plane kd is (RR + kd + 1) mod K, RR the
+// input plane's position in the rotation.  Kernel plane K - 1 starts its
+// slot's output plane: the first term of each output row (tap row K - 1,
+// column 0) is written, not added, so slots are never cleared.
+template <int K, int R, int S, int RR>
+__device__ __forceinline__ void band_fma_planes(TA (&acc)[K][R][4], const TA (&rows)[R + K - 1][4],
+                                                const TA (&tv)[K * K * K], int kd_lo, int kd_hi) {
+  constexpr int NW = K + 3;
+  constexpr int NC = row_chunks<K, S>();
+  static_for<0, R + K - 1>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    TA ch[4 * NC];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) ch[d] = rows[t][d];
+#pragma unroll
+    for (int k = 1; k < NC; ++k)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) ch[4 * k + d] = from_next_lane(ch[4 * (k - 1) + d]);
+    TA w[NW];
+#pragma unroll
+    for (int e = 0; e < NW; ++e) w[e] = ch[S + e];
+    static_for<0, K>([&](auto kc) {
+      constexpr int kd = decltype(kc)::value;
+      constexpr int slot = (RR + kd + 1) % K;
+      if (kd >= kd_lo && kd <= kd_hi) {
+        static_for<cmax(0, t - K + 1), cmin(R - 1, t) + 1>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          constexpr int a = j + K - 1 - t;  // tap row
+          static_for<0, K>([&](auto bc) {
+            constexpr int b = decltype(bc)::value;
+            const TA kv = tv[(kd * K + a) * K + b];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              if constexpr (kd == K - 1 && a == K - 1 && b == 0)
+                acc[slot][j][c] = IO::mul(kv, w[c + K - 1 - b]);
+              else
+                acc[slot][j][c] = IO::mac(acc[slot][j][c], kv, w[c + K - 1 - b]);
+            }
+          });
+        });
+      }
+    });
+  });
+}
+
+// Rank 3 with a K x K x K kernel: 2.5-D rolling planes.
+//
+// An item is a band of R output rows by 4 * LO columns for a run of DZ
+// consecutive output planes (the last run may be shorter).  The wave is split
+// into 64 / L groups of L lanes (L = 64, 32 or 16; lg = log2 L), one item
+// each, consecutive items side by side: for rows a little wider than one
+// wave's 4 * (64 - NC + 1) columns this wastes fewer lanes than whole-wave
+// strips.  The last NC - 1 lanes of a group only load (their windows would
+// reach into the next group), LO = L - NC + 1.
+//
+// The wave walks the input planes that feed its run once each, in order;
+// input plane i (counted from the run's first, od0 + offd - (K - 1)) adds into
+// output planes m = i + kd - (K - 1), kd = 0..K-1, held in K accumulator slots
+// in rotation (slot of m: m mod K); terms for planes outside the run are not
+// formed.  Output plane m has all its terms once plane m + K - 1 is in.  It is
+// stored during the step of plane m + K, after that step's loads are issued
+// and before its products, which start the slot afresh.  Each step first
+// issues the loads of the plane K - 1 ahead (a ring of K row buffers), so the
+// loads of the next K - 1 planes are in flight while the current plane's
+// products run.  The run is unrolled whole: buffers, slots and the first
+// planes' kernel-plane bounds are static and no load is in flight across a
+// loop edge.  Every step issues the same loads (a plane past the run or
+// outside the image reloads one inside, unused), so the compiler waits for
+// one plane's rows without waiting for the next ones'.
+//
+// Rows and chunks outside the image are read through the plane's buffer
+// resource at an out-of-range offset, which reads zero (W is a multiple of 4,
+// so no chunk straddles the edge; planes are below 2 GiB).  The K^3 taps are
+// held in vector registers: wave-uniform, but the scalar registers cannot keep
+// them all, and reloading them would stall every step.
+template <int K, int R, int S, int DZ>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void conv3d_rows(RowArgs a, int lg) {
+  constexpr int NC = row_chunks<K, S>();
+  constexpr int NR = R + K - 1;
+  const int L = 1 << lg;
+  const int LO = L - NC + 1;
+  const int lane = threadIdx.x;
+  const int gi = lane >> lg, gl = lane & (L - 1);
+  const int64_t Gd = gridDim.x, g = blockIdx.x;
+  const int64_t wave = (Gd % 8 == 0) ? (g % 8) * (Gd / 8) + g / 8 : g;
+  if (wave >= a.n_items) return;
+  // waves: run-major; inside a run, item q = (band, strip) with band-major order
+  const int per_run = a.n_bands * a.n_cw;
+  const int wpr = (per_run + (64 >> lg) - 1) >> (6 - lg);
+  const int run = (int)(wave / wpr);
+  const int q = (int)(wave - (int64_t)run * wpr) * (64 >> lg) + gi;
+  const bool active = q < per_run;
+  const int qe = active ? q : per_run - 1;  // an idle group reloads a valid item and stores nothing
+  const int band = qe / a.n_cw;
+  const int cw = qe - band * a.n_cw;
+  const int o0 = band * R;
+  const int p_group = cw * 4 * LO;
+  const int p_lane = p_group + 4 * gl;
+  const int chunk0 = p_group + a.off1 - (K - 1) - S;
+  const int cc = chunk0 + 4 * gl;
+  const int i0 = o0 + a.off0 - (K - 1);
+  const bool chunk_in = cc >= 0 && cc < a.W;
+  const int od0 = run * DZ;
+  const int nz = DZ < a.OD - od0 ? DZ : a.OD - od0;  // output planes of this run
+  const int n_in = nz + K - 1;                          // input planes walked
+  const int xd0 = od0 + a.offd - (K - 1);
+  const cptr<TA> taps = (cptr<TA>)(static_cast<const TA*>(a.k));
+  TA tv[K * K * K];
+#pragma unroll
+  for (int n = 0; n < K * K * K; ++n) {
+    tv[n] = taps[n];
+    asm volatile("" : "+v"(tv[n]));
+  }
+
+  // this lane's output rows: byte offsets within an output plane, and which
+  // exist
+  uint32_t yoff[R];
+  bool row_ok[R];
+  const bool writer = active && gl < LO;
+  const bool full4 = p_lane + 3 < a.OW;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    yoff[j] = (uint32_t)(((int64_t)(o0 + j) * a.ys0 + p_lane) * (int64_t)sizeof(TA));
+    row_ok[j] = writer && o0 + j < a.OH && p_lane < a.OW;
+  }
+
+  TA acc[K][R][4];
+  // store output plane m of the run (if it is one) from pl
+  auto store_plane = [&](int m, const TA (&pl)[R][4]) {
+    if (m >= 0 && m < nz) {  // uniform
+      char* yp = reinterpret_cast<char*>(a.y) + (int64_t)(od0 + m) * a.ysd * (int64_t)sizeof(TA);
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        if (row_ok[j]) {
+          if (full4) {
+            tav4 v;
+            v.x = pl[j][0];
+            v.y = pl[j][1];
+            v.z = pl[j][2];
+            v.w = pl[j][3];
+            *(__attribute__((address_space(1))) tav4*)(yp + (uint64_t)yoff[j]) = v;
+          } else {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+              if (p_lane + c < a.OW)
+                *(__attribute__((address_space(1))) TA*)(yp + (uint64_t)(yoff[j] + 4u * c)) = pl[j][c];
+          }
+        }
+      }
+    }
+  };
+
+  // byte offsets of this lane's chunks in the NR rows of a plane
+  uint32_t off[NR];
+#pragma unroll
+  for (int t = 0; t < NR; ++t) {
+    const int row = i0 + t;
+    off[t] = (chunk_in && row >= 0 && row < a.H)
+                 ? (uint32_t)(((int64_t)row * a.xs0 + cc) * (int64_t)sizeof(TX))
+                 : kOutside;
+  }
+  const uint32_t plane_bytes = (uint32_t)(((int64_t)(a.H - 1) * a.xs0 + a.W) * (int64_t)sizeof(TX));
+  // issue the loads of input plane i into dst; false when the plane lies
+  // outside the image (the nearest plane inside is read instead)
+  auto load_plane = [&](int i, TA (&dst)[NR][4]) -> bool {
+    const int xd = xd0 + i;
+    const int xc = xd < 0 ? 0 : (xd >= a.D ? a.D - 1 : xd);
+    load_band<NR>(dst, make_rsrc(static_cast<const TX*>(a.x) + (int64_t)xc * a.xsd, plane_bytes), off);
+    return xd >= 0 && xd < a.D;
+  };
+  // every input plane of the run has a row buffer, and all their loads are
+  // issued first: a wave then waits for memory once, not once per plane
+  // (a plane past a shorter last run reloads the run's last plane, unused)
+  constexpr int NB = DZ + K - 1;
+  TA rows[NB][NR][4];
+  bool have[NB];
+  static_for<0, NB>([&](auto pc) {
+    constexpr int p0 = decltype(pc)::value;
+    have[p0] = load_plane(p0 < n_in ? p0 : n_in - 1, rows[p0]);
+  });
+  static_for<0, NB>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int cur = i % K, nxt = (i + 1) % K;
+    if (i < n_in) {                  // uniform: the last run may be shorter
+      store_plane(i - K, acc[cur]);  // complete since plane i - 1; slot (i - K) mod K
+      if (have[i]) {
+        constexpr int kd_lo = K - 1 - i;       // below: planes before the run
+        const int kd_hi = nz - 1 - i + K - 1;  // above: planes after it
+        band_fma_planes<K, R, S, cur>(acc, rows[i], tv, kd_lo, kd_hi);
+      } else {
+        // a plane outside the image: its terms are zero, and it would have
+        // started output plane i's slot
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[cur][j][c] = (TA)0;
+      }
+      if (i == n_in - 1) store_plane(i - (K - 1), acc[nxt]);
+    }
+  });
+}
+
+#ifndef TC_CONV3D_WAVES
+#define TC_CONV3D_WAVES 2048
+#endif
+constexpr int64_t kConv3dWaves = TC_CONV3D_WAVES;
+
+template <int K, int R, int S>
+hipError_t launch_rows3d_s(RowArgs ra, hipStream_t s) {
+  constexpr int NC = row_chunks<K, S>();
+  ra.n_bands = (ra.OH + R - 1) / R;
+  // the group width that needs the fewest waves per plane
+  int best_lg = 6, best_cw = 0;
+  int64_t best_w = INT64_MAX;
+  for (int lg = 6; lg >= 4; --lg) {
+    const int LO = (1 << lg) - NC + 1;
+    const int n_cw = (ra.OW + 4 * LO - 1) / (4 * LO);
+    const int64_t w = ((int64_t)ra.n_bands * n_cw + (64 >> lg) - 1) >> (6 - lg);
+    if (w < best_w) best_w = w, best_lg = lg, best_cw = n_cw;
+  }
+  ra.n_cw = best_cw;
+  // runs of 2 output planes if their waves all fit at once, else of 3
+  const int dz = (int64_t)((ra.OD + 1) / 2) * best_w <= kConv3dWaves ? 2 : 3;
+  const int n_runs = (ra.OD + dz - 1) / dz;
+  ra.n_items = (int64_t)n_runs * best_w;  // waves
+  const int64_t grid = (ra.n_items + 7) / 8 * 8;
+  if (dz == 2)
+    hipLaunchKernelGGL((conv3d_rows<K, R, S, 2>), dim3((unsigned)grid), dim3(64), 0, s, ra, best_lg);
+  else
+    hipLaunchKernelGGL((conv3d_rows<K, R, S, 3>), dim3((unsigned)grid), dim3(64), 0, s, ra, best_lg);
+  return hipGetLastError();
+}
+
+template <int K, int R>
+hipError_t launch_rows3d_t(const RowArgs& ra, hipStream_t s) {
+  switch ((((ra.off1 - (K - 1)) % 4) + 4) % 4) {
+    case 0: return launch_rows3d_s<K, R, 0>(ra, s);
+    case 1: return launch_rows3d_s<K, R, 1>(ra, s);
+    case 2: return launch_rows3d_s<K, R, 2>(ra, s);
+    default: return launch_rows3d_s<K, R, 3>(ra, s);
+  }
+}
+
 template <int KH, int KW, int R, int S>
 hipError_t launch_rows_s(RowArgs ra, hipStream_t s) {
   constexpr int LO = row_lanes_out<KW, S>();
@@ -262,6 +554,11 @@ hipError_t launch_rows_t(const RowArgs& ra, hipStream_t s) {
 hipError_t TC_ROWS_LAUNCHER_X(TC_ROWS_DT)(const RowArgs& ra, int KH, hipStream_t s) {
   const int64_t items8 = (int64_t)ra.OD * ((ra.OH + 7) / 8) * ((ra.OW + 4 * 61 - 1) / (4 * 61));
   const bool small = items8 < 2048;
+  // a 3 x 3 x 3 kernel over several planes: rolling planes, each read once
+  if (KH == 3 && ra.KD == 3 && ra.OD > 1 && ra.W % 4 == 0 && ra.W >= 4 &&
+      ((int64_t)(ra.H - 1) * ra.xs0 + ra.W) * (int64_t)sizeof(TX) < (1LL << 31) &&
+      ((int64_t)(ra.OH - 1) * ra.ys0 + ra.OW) * 4 < (1LL << 31))
+    return launch_rows3d_t<3, 4>(ra, s);
   switch (KH) {
     case 2: return small ? launch_rows_t<2, 2, 4>(ra, s) : launch_rows_t<2, 2, 8>(ra, s);
     case 3: return small ? launch_rows_t<3, 3, 4>(ra, s) : launch_rows_t<3, 3, 8>(ra, s);

@@ -164,6 +164,25 @@ def test_conv_benchmark_sizes_sampled(api, N, K):
     assert np.all(np.abs(got - ref) <= bound)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "u8", "f16"])
+def test_conv3d_rolling_runs(api, dtype):
+    """3 x 3 x 3 kernels over enough planes that a wave walks a run of several
+    output planes (each input plane loaded once and added into the three
+    output planes it feeds); the last run of each mode is shorter than the
+    others.  Every output element against the oracle."""
+    xs, ks = (100, 130, 300), (3, 3, 3)
+    x = synth.conv_image(xs, case=36, dtype=dtype)
+    for mode in ("full", "same", "valid"):
+        if dtype == "u8":
+            k = synth.conv_kernel(ks, case=36, dtype="i32")
+            y = api.conv_nd_ex(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode, k_host=k).cpu().numpy()
+            np.testing.assert_array_equal(y.astype(np.int64), O.conv(x, k, mode))
+        else:
+            k = synth.conv_kernel(ks, case=36)
+            y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+            _check_float(y, x, k, mode, f"{dtype} 3d runs {mode}")
+
+
 def test_conv3d_benchmark_size_sampled(api):
     x = synth.conv_image((64, 256, 256), case=300)
     k = synth.conv_kernel((3, 3, 3), case=300)
