@@ -610,7 +610,9 @@ def serving_bench(api, torch, args):
     nowrap = [r for r in ok if r.k % specs[r.stream].n_frames != 0]
     rel = [abs(r.pick["ttc"] - specs[r.stream].ttc) / specs[r.stream].ttc for r in nowrap]
 
-    # a sample of served pairs solved again, each alone in its own plan: bitwise equal
+    # a sample of served pairs solved again, each alone in its own plan with
+    # the server's launch shape (the band height sets the blocking of the FP32
+    # sums): bitwise equal
     rng = np.random.default_rng(5)
     sample = [pairs[i] for i in rng.choice(len(pairs), size=min(32, len(pairs)), replace=False)]
     equal = True
@@ -618,7 +620,7 @@ def serving_bench(api, torch, args):
         fr = host[r.stream]
         F = fr.shape[0]
         pair = torch.stack([fr[(r.k - 1) % F], fr[r.k % F]]).cuda()
-        lv, pk = api.ttc_solve_batched([pair], levels)
+        lv, pk = api.ttc_solve_batched([pair], levels, tuning=ex.tuning)
         equal &= pk[0].tobytes() == r.pick.tobytes() and lv.tobytes() == r.levels.tobytes()
     mean_px = float(np.mean([s.H * s.W for s in specs]))
     return {
@@ -783,7 +785,7 @@ def main():
             "frac": round(ach_gb / HBM_PEAK_GBPS, 4)}
     roof["traffic"] = profiled_traffic()
     rh, gpc = tuning if tuning else api.tuning_default(torch.float16, LEVELS)
-    roof["kernel"] = f"ttc_fused<_Float16, {LEVELS}, {rh}>"
+    roof["kernel"] = f"ttc_fused (f16 frames, {LEVELS} levels)"
     roof["launch"] = {"band_rows": rh, "groups_per_cu": gpc}
     roof["kernel_ms"] = round(fused_avg, 4)
     roof["kernel_ms_source"] = "HIP events on the launch stream around the fused launch, mean over the timed steps"
@@ -808,12 +810,19 @@ def main():
     plain = None
     if not args.no_plain and not args.profile:
         plain_ms, plain_lv, plain_pk = plain_path(api, torch, vids)
-        # the same pairs through the batched plan: equal accuracy means equal results
+        # the same pairs through the batched plan.  A single pair runs in
+        # 16-row bands (latency), the batch in the tuned taller bands, so the
+        # FP32 sums are blocked differently: the records agree within the
+        # sums' error bound, not bit for bit; statuses and the multi-scale
+        # choice must be equal.
         ppk = api.decode_picks(plain_pk)
         bpk = api.decode_picks(plan.picks_buf[: plan.n_pairs * 56])
         both = (ppk["status"] == 0) & (bpk["status"] == 0)
         plain = {"ms_per_step": round(plain_ms, 3), "Gpixel_per_s": round(pair_px / (plain_ms * 1e-3) / 1e9, 3),
                  "launches_per_step": 2 * int(plan.n_pairs),
+                 "band_rows": {"single_pair": 16, "batched": int(rh)},
+                 "status_equal_batched": bool(np.array_equal(ppk["status"], bpk["status"])),
+                 "level_equal_batched": bool(np.array_equal(ppk["level"], bpk["level"])),
                  "picks_bitwise_equal_batched": bool(ppk.tobytes() == bpk.tobytes()),
                  "max_rel_ttc_diff_vs_batched": float(np.max(np.abs(ppk["ttc"][both] - bpk["ttc"][both])
                                                              / np.abs(bpk["ttc"][both]))) if both.any() else None}
