@@ -11,7 +11,9 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libttcconv.so")
+# the in-tree build; TC_LIBRARY names another build of the same library (the
+# host-sanitizer build of `build.build_sanitized`, for instance)
+LIB_PATH = os.environ.get("TC_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libttcconv.so")
 
 TC_OK, TC_SINGULAR, TC_NEED_PREV, TC_NONFINITE = 0, 1, 2, 3
 TC_EINVAL, TC_ESHAPE, TC_EDTYPE, TC_EOVERFLOW, TC_ENOMEM, TC_EDEVICE = -1, -2, -3, -4, -5, -6

@@ -79,5 +79,53 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
     return LIB
 
 
+# ----------------------------------------------------------------------------- host sanitizers
+SAN_DIR = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libttcconv_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def sanitizer_runtimes() -> list:
+    """Paths of g++'s ASan and UBSan runtimes (to preload into an uninstrumented
+    Python), or [] when they are not installed."""
+    out = []
+    for name in ("libasan.so", "libubsan.so"):
+        r = subprocess.run(["g++", f"-print-file-name={name}"], capture_output=True, text=True)
+        path = r.stdout.strip()
+        if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+            return []
+        out.append(path)
+    return out
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The library with its host code -- argument validation, shape rules,
+    planning, the tuning table, the dispatcher -- built by g++ with AddressSanitizer
+    and UndefinedBehaviorSanitizer (the device objects are the regular build's,
+    which is built first if missing).  Host code only: no device code is
+    instrumented.  Load it with TC_LIBRARY=<path> and the runtimes of
+    `sanitizer_runtimes()` preloaded; returns its path."""
+    objs = [os.path.join(BUILD, n + ".o") for _, n, _ in FUSED + ROWS] + \
+           [os.path.join(BUILD, s + ".o") for s in SOURCES if s.endswith(".hip")]
+    if not all(os.path.exists(o) for o in objs):
+        build(verbose)
+    os.makedirs(SAN_DIR, exist_ok=True)
+    host_obj = os.path.join(SAN_DIR, "ttcconv.o")
+    cmd = ["g++", "-std=c++17", "-fPIC", "-O1", "-g", *SAN_FLAGS, "-D__HIP_PLATFORM_AMD__",
+           "-I", "/opt/rocm/include", "-I", INCLUDE, "-c", os.path.join(CSRC, "ttcconv.cpp"), "-o", host_obj]
+    link = ["g++", "-shared", *SAN_FLAGS, host_obj, *objs, "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib",
+            "-lamdhip64", "-o", SAN_LIB]
+    for c in (cmd, link):
+        if verbose:
+            print(" ".join(c), flush=True)
+        r = subprocess.run(c, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitizer build failed:\n{r.stdout}\n{r.stderr}")
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
