@@ -321,44 +321,67 @@ def conv_sweep(api, torch, steps, use_graph=True):
 
 
 def fft_crossover(api, torch, steps):
-    """Direct convolution against the FFT branch on a 2048 x 2048 FP32 image,
-    full mode, square N(0,1) kernels of growing size: graph-replayed time per
-    launch of each, and the smallest kernel size at which the FFT branch wins
-    (the paper's hybrid threshold, re-measured)."""
+    """Direct convolution against the FFT branch, full mode, FP32, N(0,1)
+    kernels of growing size: on a 2048 x 2048 image (square kernels) and on a
+    64 x 256 x 256 volume (cubic kernels); graph-replayed time per launch of
+    each, the padded transform extents, and the smallest kernel size at which
+    the FFT branch wins (the paper's hybrid threshold, re-measured)."""
     import numpy as np
 
-    n = 2048
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        reps = max(steps, 10)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        del g
+        return round(e0.elapsed_time(e1) / reps, 4)
+
+    def sweep(xs, sizes, rng):
+        x = torch.from_numpy(rng.uniform(0, 1, xs).astype(np.float32)).cuda()
+        rows = []
+        for K in sizes:
+            ks = (K,) * len(xs)
+            k = torch.from_numpy(rng.normal(0, 1, ks).astype(np.float32)).cuda()
+            y = torch.empty(tuple(a + K - 1 for a in xs), device="cuda")
+            ws = torch.empty(api.conv_fft_workspace_size(x, k, "full"), dtype=torch.uint8, device="cuda")
+            res = {"K": K, "padded": [_fft_extent(a + K - 1) for a in xs]}
+            res["direct_ms"] = timed(lambda: api.conv_nd(x, k, "full", out=y))
+            res["fft_ms"] = timed(lambda: api.conv_fft(x, k, "full", out=y, ws=ws))
+            rows.append(res)
+            del k, y, ws
+            torch.cuda.empty_cache()
+        wins = [r["K"] for r in rows if r["fft_ms"] < r["direct_ms"]]
+        return {"cases": rows, "fft_wins_from_K": min(wins) if wins else None}
+
     rng = np.random.default_rng(13)
-    x = torch.from_numpy(rng.uniform(0, 1, (n, n)).astype(np.float32)).cuda()
-    rows = []
-    for K in (7, 15, 17, 23, 31, 33, 35, 37, 39, 43, 47, 63, 95):
-        k = torch.from_numpy(rng.normal(0, 1, (K, K)).astype(np.float32)).cuda()
-        y = torch.empty((n + K - 1, n + K - 1), device="cuda")
-        ws = torch.empty(api.conv2d_fft_workspace_size(x, k, "full"), dtype=torch.uint8, device="cuda")
-        res = {"K": K}
-        for name, fn in (("direct_ms", lambda: api.conv_nd(x, k, "full", out=y)),
-                         ("fft_ms", lambda: api.conv2d_fft(x, k, "full", out=y, ws=ws))):
-            fn()
-            torch.cuda.synchronize()
-            reps = max(steps, 10)
-            g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g):
-                for _ in range(reps):
-                    fn()
-            g.replay()
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            g.replay()
-            e1.record()
-            torch.cuda.synchronize()
-            res[name] = round(e0.elapsed_time(e1) / reps, 4)
-            del g
-        rows.append(res)
-        del k, y, ws
-        torch.cuda.empty_cache()
-    wins = [r["K"] for r in rows if r["fft_ms"] < r["direct_ms"]]
-    return {"image": f"{n}x{n} f32, full mode", "cases": rows, "fft_wins_from_K": min(wins) if wins else None}
+    out = {"image": "2048x2048 f32, full mode"}
+    out.update(sweep((2048, 2048), (7, 15, 17, 19, 23, 27, 31, 33, 35, 37, 39, 43, 47, 63, 95), rng))
+    out["volume_3d"] = {"volume": "64x256x256 f32, full mode"}
+    out["volume_3d"].update(sweep((64, 256, 256), (3, 5, 7, 9, 11, 13, 15), rng))
+    return out
+
+
+def _fft_extent(n):
+    """The padded transform extent of the FFT branch: the smallest 2^a 3^b 5^c >= n."""
+    m = max(1, n)
+    while True:
+        r = m
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return m
+        m += 1
 
 
 def gradient_sweep(api, torch, steps):

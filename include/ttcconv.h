@@ -112,7 +112,8 @@ int tc_device_check(int device, int* n_cu);
  *                          of tc_conv_workspace_size, TC_ENOMEM if smaller);
  *          TC_CONV_AUTO    the FFT branch when it applies, the kernel's longest
  *                          side is >= fft_threshold (0: the library's measured
- *                          crossover) and the workspace is large enough; else,
+ *                          crossover for the rank) and the workspace is large
+ *                          enough; else,
  *                          when k_host is given and k is a square F32 2-D
  *                          kernel of 3, 5, 7, 9, 11 or 15 taps that passes the
  *                          rank-one test of tc_conv_kernel_rank1 with tolerance
@@ -176,21 +177,29 @@ int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, const tc_tensor
                          const tc_tensor* y, void* stream);
 
 /* ------------------------------------------------------------------------
- * FFT branch of 2-D convolution
+ * FFT branch of 2-D and 3-D convolution
  *
  * Convolutions section: by the convolution theorem y = F^-1(F(x) F(k)), the
  * route the paper's hybrid FastConv takes for kernels above a size threshold
- * (Accelerating Convolutions).  The result, modes and output extents are those
- * of tc_conv_nd for 2-D F32 x and k; x and k are zero-padded to P x Q, the
- * powers of two >= (H+KH-1) x (W+KW-1), transformed (radix-4 Stockham, FP32,
- * twiddles from sincospi), multiplied, transformed back and cut to the mode.
- * P and Q are at most 4096 (TC_ESHAPE beyond).  x and y may be strided; k is
- * contiguous device memory.  ws: device workspace of
- * tc_conv2d_fft_workspace_size bytes (three P x Q complex planes and two
- * twiddle tables; TC_ENOMEM if smaller).  Error: norm-wise, about
- * log2(P Q) * 2^-24 * ||x||_2 ||k||_1 per output (not the element-wise bound of
- * the direct path).  Launches only.
+ * (Accelerating Convolutions); the Future Work section's n-dimensional
+ * extension, here for rank 2 and rank 3.  The result, modes and output
+ * extents are those of tc_conv_nd for F32 x and k of equal rank (2 or 3).
+ * Each axis is zero-padded to the smallest 2^a 3^b 5^c that holds the full
+ * output (x extent + k extent - 1), at most 4096 (TC_ESHAPE beyond); x and k
+ * are transformed (mixed-radix Stockham, radix 2, 3, 4 and 5, FP32, twiddles
+ * rounded from FP64), multiplied, transformed back and cut to the mode.  x and
+ * y may be strided; k is contiguous device memory.  ws: device workspace of
+ * tc_conv_fft_workspace_size bytes (three complex volumes of the padded size
+ * and one twiddle table per axis; TC_ENOMEM if smaller).  Error: norm-wise,
+ * about 2^-24 * (the transform's stage count) * ||x||_2 ||k||_1 per output (not
+ * the element-wise bound of the direct path).  Launches only.
+ *
+ * tc_conv2d_fft_workspace_size / tc_conv2d_fft: the same for rank 2 only
+ * (TC_ESHAPE for other ranks).
  * ------------------------------------------------------------------------ */
+int tc_conv_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes);
+int tc_conv_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws,
+                size_t ws_bytes, void* stream);
 int tc_conv2d_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes);
 int tc_conv2d_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws,
                   size_t ws_bytes, void* stream);

@@ -100,6 +100,8 @@ SIGNATURES = {
     "tc_conv_nd": (_I, [_T, _T, _I32, _T, _P]),
     "tc_conv_workspace_size": (_I, [_T, _T, _I32, _I32, C.POINTER(_SZ)]),
     "tc_conv_nd_ex": (_I, [_T, _T, _I32, _T, C.POINTER(TcConvOpts), _P]),
+    "tc_conv_fft_workspace_size": (_I, [_T, _T, _I32, C.POINTER(_SZ)]),
+    "tc_conv_fft": (_I, [_T, _T, _I32, _T, _P, _SZ, _P]),
     "tc_conv2d_fft_workspace_size": (_I, [_T, _T, _I32, C.POINTER(_SZ)]),
     "tc_conv2d_fft": (_I, [_T, _T, _I32, _T, _P, _SZ, _P]),
     "tc_pyramid_shape": (_I, [_I64, _I64, _I32, C.POINTER(_I64), C.POINTER(_I64)]),

@@ -184,10 +184,33 @@ def conv_nd_auto(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Opti
 SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
 
 # Kernel side length from which the FFT branch beats the direct kernels on
-# MI355X (2048 x 2048 FP32 images, full mode, square kernels; bench.py's
-# crossover sweep: direct 0.58 ms against FFT 0.59 ms at 35, 0.62 against 0.60
-# at 37).
-FFT_THRESHOLD = 37
+# MI355X (FP32, full mode, cubic kernels; bench.py's crossover sweeps): 2048 x
+# 2048 images, and 64 x 256 x 256 volumes.  The library's dispatcher
+# (tc_conv_nd_ex) uses the same values.
+FFT_THRESHOLD = 27
+FFT_THRESHOLD_3D = 9
+FFT_MAX_N = 4096
+
+
+def conv_fft_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full") -> int:
+    n = C.c_size_t(0)
+    L.check("tc_conv_fft_workspace_size",
+            _lib().tc_conv_fft_workspace_size(C.byref(_desc(x)), C.byref(_desc(k)), L.MODES[mode], C.byref(n)))
+    return n.value
+
+
+def conv_fft(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Optional[torch.Tensor] = None,
+             ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """2-D or 3-D FP32 convolution through the FFT branch (same result and modes as conv_nd)."""
+    if out is None:
+        out = torch.empty(conv_out_shape(tuple(x.shape), tuple(k.shape), mode), dtype=torch.float32, device=x.device)
+    nbytes = conv_fft_workspace_size(x, k, mode)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=x.device)
+    L.check("tc_conv_fft", _lib().tc_conv_fft(C.byref(_desc(x)), C.byref(_desc(k)), L.MODES[mode],
+                                              C.byref(_desc(out)), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                              _stream(stream)))
+    return out
 
 
 def conv2d_fft_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full") -> int:
@@ -211,16 +234,24 @@ def conv2d_fft(x: torch.Tensor, k: torch.Tensor, mode: str = "full", out: Option
     return out
 
 
+def conv_hybrid(x: torch.Tensor, k: torch.Tensor, mode: str = "full", threshold: Optional[int] = None,
+                out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """The paper's hybrid: direct convolution for kernels smaller than
+    `threshold` on their longest side (default: the measured crossover of the
+    rank), the FFT branch from there on (2-D and 3-D FP32, when the padded
+    transform fits, else direct)."""
+    if x.dim() in (2, 3) and x.dim() == k.dim() and x.dtype == torch.float32:
+        thr = threshold if threshold is not None else (FFT_THRESHOLD if x.dim() == 2 else FFT_THRESHOLD_3D)
+        fits = all(a + b - 1 <= FFT_MAX_N for a, b in zip(x.shape, k.shape))
+        if max(k.shape) >= thr and fits:
+            return conv_fft(x, k, mode, out=out, stream=stream)
+    return conv_nd(x, k, mode, out=out, stream=stream)
+
+
 def conv2d_hybrid(x: torch.Tensor, k: torch.Tensor, mode: str = "full", threshold: int = FFT_THRESHOLD,
                   out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """The paper's hybrid: direct convolution for kernels smaller than
-    `threshold` on their longer side, the FFT branch from there on (when the
-    padded transform fits, else direct)."""
-    if x.dim() == 2 and x.dtype == torch.float32 and max(k.shape) >= threshold:
-        fits = all(a + b - 1 <= 4096 for a, b in zip(x.shape, k.shape))
-        if fits:
-            return conv2d_fft(x, k, mode, out=out, stream=stream)
-    return conv_nd(x, k, mode, out=out, stream=stream)
+    """conv_hybrid for 2-D images."""
+    return conv_hybrid(x, k, mode, threshold, out=out, stream=stream)
 
 
 # ----------------------------------------------------------------------------- pyramid / derivatives

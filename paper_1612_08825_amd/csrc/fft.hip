@@ -1,17 +1,30 @@
-// FFT branch of 2-D convolution (Convolutions section: the convolution theorem,
-// y = F^-1(F(x) F(k)); Accelerating Convolutions: the hybrid that switches to
-// it for large kernels).
+// FFT branch of 2-D and 3-D convolution (Convolutions section: the convolution
+// theorem, y = F^-1(F(x) F(k)); Accelerating Convolutions: the hybrid that
+// switches to it for large kernels; Future Work: the n-dimensional extension).
 //
-// fft_twiddles: w[k] = exp(-2 pi i k / N), k < N, with sincospi (exact
-//               argument k/N for N a power of two).
-// fft_rows:     Stockham transform of length N = 2^m <= 4096 along each row,
-//               one work-group per row, the row held in LDS: one radix-2
-//               stage when m is odd, then radix-4 stages (described in the
-//               kernel).  The inverse uses conjugate twiddles and no scale.
+// x and k are zero-padded to a volume n0 x .. x n_{d-1} (d = 2 or 3) whose
+// extents are 2^a 3^b 5^c, at least the full output's, at most kFftMaxN each.
+// A d-dimensional transform is d passes of 1-D transforms along the last axis,
+// with a 2-D transpose between passes that moves the transformed axis out of
+// the way:
+//   forward: rows along n_{d-1}; [rest][n_{d-1}] -> [n_{d-1}][rest]; rows along
+//            n_{d-2}; ...; rows along n_0.  The spectrum is left in the order
+//            (n_1, .., n_{d-1}, n_0): the inverse undoes it without a final
+//            transpose.
+//   inverse: rows along n_0; [first][rest] -> [rest][first]; rows along n_1;
+//            ...; the last pass (along n_{d-1}, back in the original order)
+//            transforms only the rows of the mode's window and writes their
+//            real part, scaled by 1 / (n_0 .. n_{d-1}), straight into y.
+// The first forward pass reads the real image (or kernel) and pads it with
+// zeros in LDS.
+//
+// fft_twiddles: w[m] = exp(-2 pi i m / N), m < N, evaluated in FP64 and rounded.
+// fft_rows:     a Stockham transform of kFftMaxN / N rows per work-group (at
+//               least one), the rows in LDS, in stages of radix 4, 2, 3 and 5
+//               (the stage list comes from the host; described at
+//               fft_stage).  The inverse uses conjugate twiddles and no scale.
 // transpose_c:  complex R x C -> C x R through 32 x 33 LDS tiles.
-// mul_c:        the pointwise product.  The first forward pass reads the real
-//               image and pads it in LDS; the last inverse pass writes the real
-//               part, scaled by 1/(P Q), of the mode's window straight into y.
+// mul_c:        the pointwise product of the two spectra.
 #include <math.h>
 
 #include "device_common.hpp"
@@ -21,229 +34,355 @@ namespace ttc {
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kFftPerThread = kFftMaxN / 2 / kFftThreads;   // radix-2 butterflies per thread (max)
-constexpr int kFftPerThread4 = kFftMaxN / 4 / kFftThreads;  // radix-4 butterflies per thread (max)
 
 __global__ __launch_bounds__(256) void fft_twiddles(float2* __restrict__ tw, int N) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= N) return;
-  float s, c;
-  sincospif(-2.0f * (float)k / (float)N, &s, &c);
-  tw[k] = make_float2(c, s);
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  double s, c;
+  sincospi(-2.0 * (double)m / (double)N, &s, &c);
+  tw[m] = make_float2((float)c, (float)s);
 }
 
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float s, float2 a) { return make_float2(s * a.x, s * a.y); }
+// -i z for the forward transform, +i z for the inverse
 template <bool INV>
-__device__ __forceinline__ float2 cmul_tw(float2 w, float2 b) {
-  if (INV) w.y = -w.y;
-  return make_float2(w.x * b.x - w.y * b.y, w.x * b.y + w.y * b.x);
+__device__ __forceinline__ float2 mul_mi(float2 z) {
+  return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
 }
 
-// Where a row pass reads and writes besides the complex plane: IN_REAL rows
-// come from a real H x W image (zero beyond it: the padding), OUT_REAL rows
-// o0 .. o0 + OH - 1 leave as the real part times `scale`, columns o1 .. o1 +
-// OW - 1, into y (the cut of the requested mode).
+// The R-point DFT of a[0..R-1] in place: a_q <- sum_t a_t e^(-+2 pi i t q / R).
+template <int R, bool INV>
+__device__ __forceinline__ void dft_small(float2 (&a)[R]) {
+  if constexpr (R == 2) {
+    const float2 b0 = cadd(a[0], a[1]), b1 = csub(a[0], a[1]);
+    a[0] = b0;
+    a[1] = b1;
+  } else if constexpr (R == 3) {
+    constexpr float kS3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+    const float2 t1 = cadd(a[1], a[2]);
+    const float2 t2 = make_float2(a[0].x - 0.5f * t1.x, a[0].y - 0.5f * t1.y);
+    const float2 t3 = mul_mi<INV>(cscale(kS3, csub(a[1], a[2])));
+    a[0] = cadd(a[0], t1);
+    a[1] = cadd(t2, t3);
+    a[2] = csub(t2, t3);
+  } else if constexpr (R == 4) {
+    const float2 b0 = cadd(a[0], a[2]), b1 = csub(a[0], a[2]);
+    const float2 b2 = cadd(a[1], a[3]), b3 = mul_mi<INV>(csub(a[1], a[3]));
+    a[0] = cadd(b0, b2);
+    a[1] = cadd(b1, b3);
+    a[2] = csub(b0, b2);
+    a[3] = csub(b1, b3);
+  } else {
+    static_assert(R == 5, "radix 2, 3, 4 or 5");
+    constexpr float kC1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+    constexpr float kC2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+    constexpr float kS1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+    constexpr float kS2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+    const float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+    const float2 t3 = csub(a[1], a[4]), t4 = csub(a[2], a[3]);
+    const float2 r1 = make_float2(a[0].x + kC1 * t1.x + kC2 * t2.x, a[0].y + kC1 * t1.y + kC2 * t2.y);
+    const float2 r2 = make_float2(a[0].x + kC2 * t1.x + kC1 * t2.x, a[0].y + kC2 * t1.y + kC1 * t2.y);
+    const float2 i1 = mul_mi<INV>(make_float2(kS1 * t3.x + kS2 * t4.x, kS1 * t3.y + kS2 * t4.y));
+    const float2 i2 = mul_mi<INV>(make_float2(kS2 * t3.x - kS1 * t4.x, kS2 * t3.y - kS1 * t4.y));
+    a[0] = make_float2(a[0].x + t1.x + t2.x, a[0].y + t1.y + t2.y);
+    a[1] = cadd(r1, i1);
+    a[4] = csub(r1, i1);
+    a[2] = cadd(r2, i2);
+    a[3] = csub(r2, i2);
+  }
+}
+
+// One Stockham stage of radix R on nr rows in LDS (row i at buf + i N; N
+// points each, sub-transforms of length Ls done so far, N divisible by R Ls):
+// for j < N / R with k = j mod Ls, a_t = v[j + t N / R] w^(t k), w = exp(-+2 pi
+// i / (R Ls)) = tw[N / (R Ls)]; the R-point DFT of (a_t) goes to
+// v'[(j / Ls) R Ls + k + q Ls], q < R.  One table read per butterfly: w^k
+// from the table staged in LDS (k N / (R Ls) < N / 2), its higher powers by
+// multiplication.  All reads before a barrier, all writes after it.
+template <int R, bool INV>
+__device__ __forceinline__ void fft_stage(float2* buf, const float2* twl, int N, int nr, int Ls) {
+  constexpr int kPer = (kFftMaxN / R + kFftThreads - 1) / kFftThreads;
+  const int nb = N / R;
+  const int step = N / (R * Ls);
+  const int tid = threadIdx.x;
+  float2 o[kPer][R];
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int b = tid + c * kFftThreads;
+    if (b < nr * nb) {
+      const int i = b / nb, j = b - i * nb;
+      const float2* v = buf + i * N;
+      const int k = j % Ls;
+      float2 w = twl[k * step];
+      if (INV) w.y = -w.y;
+      o[c][0] = v[j];
+      float2 wt = w;
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        o[c][t] = cmul(wt, v[j + t * nb]);
+        if (t + 1 < R) wt = cmul(wt, w);
+      }
+      dft_small<R, INV>(o[c]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < kPer; ++c) {
+    const int b = tid + c * kFftThreads;
+    if (b < nr * nb) {
+      const int i = b / nb, j = b - i * nb;
+      const int k = j % Ls;
+      float2* v = buf + i * N;
+      const int base = (j / Ls) * R * Ls + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[base + q * Ls] = o[c][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Where a row pass reads and writes besides the complex volume.
+//   IN_REAL: row r = a * nb + b of the padded volume is the source row at
+//   src + a sa + b sb (element step s_in) when a < ea and b < eb, its first
+//   w_in elements, zero elsewhere (the padding).
+//   OUT_REAL: work-group g of an OA x OB grid is row (oa + g / OB) * nb +
+//   (ob + g % OB); its elements oc .. oc + ow - 1 go, real part times scale,
+//   to y + (g / OB) ya + (g % OB) yb + i yc.
 struct RowIO {
-  const float* x;
-  int64_t xs0, xs1;
-  int H, W;
+  const float* src;
+  int64_t sa, sb, s_in;
+  int ea, eb, w_in;
+  int nb;
   float* y;
-  int64_t ys0, ys1;
-  int OH, OW, o0, o1;
+  int64_t ya, yb, yc;
+  int OA, OB, oa, ob, oc, ow;
   float scale;
 };
 
+// A work-group transforms nr = max(1, kFftMaxN / N) consecutive rows (rows
+// 0 .. n_rows - 1 in all); dynamic LDS: nr N points, then N / 2 twiddles.
 template <bool INV, bool IN_REAL, bool OUT_REAL>
-__global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ data, int64_t row_stride, int N, int m,
-                                                        const float2* __restrict__ tw, RowIO io) {
-  __shared__ float2 buf[kFftMaxN];
-  // every radix-4 stage reads w^k = tw[k N / (4 Ls)] with k < Ls: the first
-  // quarter of the table, staged in LDS once
-  __shared__ float2 twl[kFftMaxN / 4];
-  const int r = OUT_REAL ? io.o0 + (int)blockIdx.x : (int)blockIdx.x;
-  float2* row = data + (int64_t)r * row_stride;
+__global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ data, FftAxis ax,
+                                                        const float2* __restrict__ tw, int64_t n_rows, RowIO io) {
+  extern __shared__ float2 lds[];
+  const int N = ax.n;
+  const int nr = N >= kFftMaxN ? 1 : kFftMaxN / N;
+  float2* buf = lds;
+  float2* twl = lds + nr * N;
+  const int64_t g0 = (int64_t)blockIdx.x * nr;
+  const int nrow = (int)(n_rows - g0 < nr ? n_rows - g0 : nr);  // rows of this work-group
   const int tid = threadIdx.x;
+  // the global row of local row i (OUT_REAL: the i-th row of the window)
+  auto row_of = [&](int i) -> int64_t {
+    const int64_t g = g0 + i;
+    if (OUT_REAL) return (int64_t)(io.oa + g / io.OB) * io.nb + (io.ob + g % io.OB);
+    return g;
+  };
   if (IN_REAL) {
-    for (int i = tid; i < N; i += kFftThreads)
-      buf[i] = make_float2((r < io.H && i < io.W) ? io.x[(int64_t)r * io.xs0 + (int64_t)i * io.xs1] : 0.f, 0.f);
+    // rows wholly in the padding transform to zero: write them and stop
+    bool any = false;
+    for (int i = 0; i < nrow; ++i) {
+      const int64_t r = row_of(i);
+      const int64_t a = r / io.nb, b = r - a * io.nb;
+      any |= a < io.ea && b < io.eb;
+    }
+    if (!any) {
+      for (int64_t e = tid; e < (int64_t)nrow * N; e += kFftThreads) data[g0 * N + e] = make_float2(0.f, 0.f);
+      return;
+    }
+    for (int e = tid; e < nr * N; e += kFftThreads) {
+      const int i = e / N, c = e - i * N;
+      float v = 0.f;
+      if (i < nrow) {
+        const int64_t r = row_of(i);
+        const int64_t a = r / io.nb, b = r - a * io.nb;
+        if (a < io.ea && b < io.eb && c < io.w_in) v = io.src[a * io.sa + b * io.sb + (int64_t)c * io.s_in];
+      }
+      buf[e] = make_float2(v, 0.f);
+    }
   } else {
-    for (int i = tid; i < N; i += kFftThreads) buf[i] = row[i];
+    for (int e = tid; e < nr * N; e += kFftThreads) {
+      const int i = e / N, c = e - i * N;
+      buf[e] = i < nrow ? data[row_of(i) * N + c] : make_float2(0.f, 0.f);
+    }
   }
-  for (int i = tid; i < (N >> 2); i += kFftThreads) twl[i] = tw[i];
+  for (int i = tid; i < (N >> 1); i += kFftThreads) twl[i] = tw[i];
   __syncthreads();
-  int lg = 0;  // log2 of the sub-transform length done so far
-  if (m & 1) {
-    // one radix-2 stage (sub-length 1: no twiddles)
-    const int half = N >> 1;
-    float2 o0[kFftPerThread], o1[kFftPerThread];
-#pragma unroll
-    for (int c = 0; c < kFftPerThread; ++c) {
-      const int j = tid + c * kFftThreads;
-      if (j < half) {
-        const float2 a = buf[j], b = buf[j + half];
-        o0[c] = make_float2(a.x + b.x, a.y + b.y);
-        o1[c] = make_float2(a.x - b.x, a.y - b.y);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < kFftPerThread; ++c) {
-      const int j = tid + c * kFftThreads;
-      if (j < half) {
-        buf[2 * j] = o0[c];
-        buf[2 * j + 1] = o1[c];
-      }
-    }
-    __syncthreads();
-    lg = 1;
-  }
-  // radix-4 stages: sub-length Ls = 2^lg; a_t = v[j + t N/4] w^(t k),
-  // w = exp(-+2 pi i / (4 Ls)) = tw[k t N / (4 Ls)], k = j mod Ls; the 4-point
-  // transform of (a_0..a_3) goes to v'[(j / Ls) 4 Ls + k + q Ls], q = 0..3
-  const int q4 = N >> 2;
-  for (; lg < m; lg += 2) {
-    const int Ls = 1 << lg;
-    const int tws = m - lg - 2;  // log2(N / (4 Ls))
-    float2 o[kFftPerThread4][4];
-#pragma unroll
-    for (int c = 0; c < kFftPerThread4; ++c) {
-      const int j = tid + c * kFftThreads;
-      if (j < q4) {
-        const int k = j & (Ls - 1);
-        // one table read per butterfly: w^2k and w^3k as products of w^k
-        const float2 w1 = twl[k << tws];
-        const float2 w2 = make_float2(w1.x * w1.x - w1.y * w1.y, 2.f * w1.x * w1.y);
-        const float2 w3 = make_float2(w2.x * w1.x - w2.y * w1.y, w2.x * w1.y + w2.y * w1.x);
-        const float2 a0 = buf[j];
-        const float2 a1 = cmul_tw<INV>(w1, buf[j + q4]);
-        const float2 a2 = cmul_tw<INV>(w2, buf[j + 2 * q4]);
-        const float2 a3 = cmul_tw<INV>(w3, buf[j + 3 * q4]);
-        const float2 b0 = make_float2(a0.x + a2.x, a0.y + a2.y), b1 = make_float2(a0.x - a2.x, a0.y - a2.y);
-        const float2 b2 = make_float2(a1.x + a3.x, a1.y + a3.y), b3 = make_float2(a1.x - a3.x, a1.y - a3.y);
-        // forward: -i b3; inverse: +i b3
-        const float2 r = INV ? make_float2(-b3.y, b3.x) : make_float2(b3.y, -b3.x);
-        o[c][0] = make_float2(b0.x + b2.x, b0.y + b2.y);
-        o[c][1] = make_float2(b1.x + r.x, b1.y + r.y);
-        o[c][2] = make_float2(b0.x - b2.x, b0.y - b2.y);
-        o[c][3] = make_float2(b1.x - r.x, b1.y - r.y);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < kFftPerThread4; ++c) {
-      const int j = tid + c * kFftThreads;
-      if (j < q4) {
-        const int k = j & (Ls - 1);
-        const int base = ((j >> lg) << (lg + 2)) + k;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) buf[base + q * Ls] = o[c][q];
-      }
-    }
-    __syncthreads();
-  }
+  // the stage list runs radix 4, then 2, then 3, then 5: one loop per radix
+  // (a switch over the radix inside one loop costs twice the registers)
+  int Ls = 1, st = 0;
+  for (; st < ax.n_stages && ax.radix[st] == 4; ++st, Ls *= 4) fft_stage<4, INV>(buf, twl, N, nr, Ls);
+  for (; st < ax.n_stages && ax.radix[st] == 2; ++st, Ls *= 2) fft_stage<2, INV>(buf, twl, N, nr, Ls);
+  for (; st < ax.n_stages && ax.radix[st] == 3; ++st, Ls *= 3) fft_stage<3, INV>(buf, twl, N, nr, Ls);
+  for (; st < ax.n_stages && ax.radix[st] == 5; ++st, Ls *= 5) fft_stage<5, INV>(buf, twl, N, nr, Ls);
   if (OUT_REAL) {
-    float* yr = io.y + (int64_t)(r - io.o0) * io.ys0;
-    for (int i = tid; i < io.OW; i += kFftThreads) yr[(int64_t)i * io.ys1] = buf[io.o1 + i].x * io.scale;
+    for (int i = 0; i < nrow; ++i) {
+      const int64_t g = g0 + i;
+      float* yr = io.y + (g / io.OB) * io.ya + (g % io.OB) * io.yb;
+      for (int c = tid; c < io.ow; c += kFftThreads) yr[(int64_t)c * io.yc] = buf[i * N + io.oc + c].x * io.scale;
+    }
   } else {
-    for (int i = tid; i < N; i += kFftThreads) row[i] = buf[i];
+    for (int e = tid; e < nrow * N; e += kFftThreads) {
+      const int i = e / N, c = e - i * N;
+      data[row_of(i) * N + c] = buf[e];
+    }
   }
 }
 
-// dst[c][r] = src[r][c] for an R x C source.
-__global__ __launch_bounds__(256) void transpose_c(const float2* __restrict__ src, int R, int C,
+// dst[c][r] = src[r][c] for an R x C source (grid.y steps over row tiles).
+__global__ __launch_bounds__(256) void transpose_c(const float2* __restrict__ src, int64_t R, int64_t C,
                                                    float2* __restrict__ dst) {
   __shared__ float2 tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const int64_t c0 = (int64_t)blockIdx.x * 32;
+  for (int64_t r0 = (int64_t)blockIdx.y * 32; r0 < R; r0 += (int64_t)gridDim.y * 32) {
 #pragma unroll
-  for (int i = 0; i < 32; i += 8) {
-    const int r = r0 + ty + i, c = c0 + tx;
-    if (r < R && c < C) tile[ty + i][tx] = src[(int64_t)r * C + c];
-  }
-  __syncthreads();
+    for (int i = 0; i < 32; i += 8) {
+      const int64_t r = r0 + ty + i, c = c0 + tx;
+      if (r < R && c < C) tile[ty + i][tx] = src[r * C + c];
+    }
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 32; i += 8) {
-    const int c = c0 + ty + i, r = r0 + tx;
-    if (c < C && r < R) dst[(int64_t)c * R + r] = tile[tx][ty + i];
+    for (int i = 0; i < 32; i += 8) {
+      const int64_t c = c0 + ty + i, r = r0 + tx;
+      if (c < C && r < R) dst[c * R + r] = tile[tx][ty + i];
+    }
+    __syncthreads();
   }
 }
 
 __global__ __launch_bounds__(256) void mul_c(float2* __restrict__ a, const float2* __restrict__ b, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float2 u = a[i], v = b[i];
-  a[i] = make_float2(u.x * v.x - u.y * v.y, u.x * v.y + u.y * v.x);
-}
-
-int ilog2(int n) {
-  int m = 0;
-  while ((1 << m) < n) ++m;
-  return m;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = cmul(a[i], b[i]);
 }
 
 template <bool INV, bool IN_REAL, bool OUT_REAL>
-hipError_t rows_t(float2* d, int n_rows, int N, const float2* tw, const RowIO& io, hipStream_t s) {
-  hipLaunchKernelGGL((fft_rows<INV, IN_REAL, OUT_REAL>), dim3((unsigned)n_rows), dim3(kFftThreads), 0, s, d,
-                     (int64_t)N, N, ilog2(N), tw, io);
+hipError_t rows_t(float2* d, int64_t n_rows, const FftAxis& ax, const float2* tw, const RowIO& io, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  const int N = ax.n;
+  const int nr = N >= kFftMaxN ? 1 : kFftMaxN / N;
+  const size_t lds = ((size_t)nr * N + (size_t)(N >> 1)) * sizeof(float2);
+  hipLaunchKernelGGL((fft_rows<INV, IN_REAL, OUT_REAL>), dim3((unsigned)((n_rows + nr - 1) / nr)), dim3(kFftThreads),
+                     lds, s, d, ax, tw, n_rows, io);
   return hipGetLastError();
 }
 
-hipError_t rows(float2* d, int n_rows, int N, const float2* tw, bool inv, hipStream_t s) {
-  const RowIO io{};
-  return inv ? rows_t<true, false, false>(d, n_rows, N, tw, io, s)
-             : rows_t<false, false, false>(d, n_rows, N, tw, io, s);
-}
-
-hipError_t transpose(const float2* src, int R, int C, float2* dst, hipStream_t s) {
-  hipLaunchKernelGGL(transpose_c, dim3((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32)), dim3(256), 0, s, src,
-                     R, C, dst);
+hipError_t transpose(const float2* src, int64_t R, int64_t C, float2* dst, hipStream_t s) {
+  const int64_t gy = (R + 31) / 32;
+  hipLaunchKernelGGL(transpose_c, dim3((unsigned)((C + 31) / 32), (unsigned)(gy < 65535 ? gy : 65535)), dim3(256),
+                     0, s, src, R, C, dst);
   return hipGetLastError();
 }
 
-// forward 2-D transform of a real H x W image zero-padded to P x Q; the
-// result is left transposed (Q x P) in `out`, `tmp` is P x Q scratch
-hipError_t forward2d(const float* x, int64_t s0, int64_t s1, int H, int W, int P, int Q, const float2* twP,
-                     const float2* twQ, float2* tmp, float2* out, hipStream_t s) {
+// The forward transform of a real array (extents e[], strides st[], leading
+// axis first) zero-padded to the volume; the spectrum ends in `out`, in the
+// order (n_1, .., n_{d-1}, n_0); `tmp` is scratch of the same size.
+hipError_t forward(const FftConv& f, const float* src, const int64_t* st, const int* e, float2* tmp, float2* out,
+                   hipStream_t s) {
+  const int d = f.rank;
+  int64_t T = 1;
+  for (int a = 0; a < d; ++a) T *= f.ax[a].n;
   RowIO io{};
-  io.x = x;
-  io.xs0 = s0;
-  io.xs1 = s1;
-  io.H = H;
-  io.W = W;
-  hipError_t e;
-  // the first pass reads the real image itself (zero-padded in LDS)
-  if ((e = rows_t<false, true, false>(tmp, P, Q, twQ, io, s)) != hipSuccess) return e;
-  if ((e = transpose(tmp, P, Q, out, s)) != hipSuccess) return e;
-  return rows(out, Q, P, twP, false, s);
+  io.src = src;
+  io.s_in = st[d - 1];
+  io.w_in = e[d - 1];
+  if (d == 2) {
+    io.nb = 1;
+    io.sa = st[0];
+    io.ea = e[0];
+    io.sb = 0;
+    io.eb = 1;
+  } else {
+    io.nb = f.ax[1].n;
+    io.sa = st[0];
+    io.ea = e[0];
+    io.sb = st[1];
+    io.eb = e[1];
+  }
+  // d - 1 transposes follow the first pass: start where the last pass must end
+  float2* cur = ((d - 1) % 2 == 0) ? out : tmp;
+  float2* other = (cur == out) ? tmp : out;
+  hipError_t err;
+  const RowIO none{};
+  if ((err = rows_t<false, true, false>(cur, T / f.ax[d - 1].n, f.ax[d - 1], f.tw[d - 1], io, s)) != hipSuccess)
+    return err;
+  for (int a = d - 1; a >= 1; --a) {
+    if ((err = transpose(cur, T / f.ax[a].n, f.ax[a].n, other, s)) != hipSuccess) return err;
+    float2* t = cur;
+    cur = other;
+    other = t;
+    if ((err = rows_t<false, false, false>(cur, T / f.ax[a - 1].n, f.ax[a - 1], f.tw[a - 1], none, s)) !=
+        hipSuccess)
+      return err;
+  }
+  return hipSuccess;
 }
 
 }  // namespace
 
-hipError_t launch_conv2d_fft(const FftConv& f, hipStream_t s) {
-  const int P = f.P, Q = f.Q;
-  hipError_t e;
-  hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, f.twP, P);
-  hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s, f.twQ, Q);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = forward2d(f.x, f.xs0, f.xs1, f.H, f.W, P, Q, f.twP, f.twQ, f.A, f.B, s)) != hipSuccess) return e;
-  if ((e = forward2d(f.k, f.KW, 1, f.KH, f.KW, P, Q, f.twP, f.twQ, f.A, f.C, s)) != hipSuccess) return e;
-  const int64_t n = (int64_t)P * Q;
-  hipLaunchKernelGGL(mul_c, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f.B, f.C, n);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = rows(f.B, Q, P, f.twP, true, s)) != hipSuccess) return e;
-  if ((e = transpose(f.B, Q, P, f.A, s)) != hipSuccess) return e;
-  // the last pass transforms only the rows of the mode's window and writes
-  // their real part, scaled, straight into y
-  if (f.OH <= 0 || f.OW <= 0) return hipSuccess;
+hipError_t launch_conv_fft(const FftConv& f, hipStream_t s) {
+  const int d = f.rank;
+  hipError_t err;
+  for (int a = 0; a < d; ++a)
+    hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((f.ax[a].n + 255) / 256)), dim3(256), 0, s, f.tw[a], f.ax[a].n);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  int64_t T = 1;
+  for (int a = 0; a < d; ++a) T *= f.ax[a].n;
+  const int64_t kst[3] = {d == 3 ? (int64_t)f.kn[1] * f.kn[2] : (int64_t)f.kn[1], d == 3 ? (int64_t)f.kn[2] : 1, 1};
+  if ((err = forward(f, f.x, f.xs, f.xn, f.A, f.B, s)) != hipSuccess) return err;
+  if ((err = forward(f, f.k, kst, f.kn, f.A, f.C, s)) != hipSuccess) return err;
+  const int64_t blocks = (T + 255) / 256;
+  hipLaunchKernelGGL(mul_c, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, f.B, f.C, T);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  // inverse, from the order (n_1, .., n_{d-1}, n_0): rows along n_0, then for
+  // each further axis a transpose [first][rest] -> [rest][first] and rows along
+  // the axis now last; d - 1 transposes, the last rows pass writes y
+  float2* cur = f.B;
+  float2* other = f.A;
+  const RowIO none{};
+  if ((err = rows_t<true, false, false>(cur, T / f.ax[0].n, f.ax[0], f.tw[0], none, s)) != hipSuccess) return err;
+  for (int a = 1; a < d; ++a) {
+    // the current first axis is n_a
+    if ((err = transpose(cur, f.ax[a].n, T / f.ax[a].n, other, s)) != hipSuccess) return err;
+    float2* t = cur;
+    cur = other;
+    other = t;
+    if (a < d - 1) {
+      if ((err = rows_t<true, false, false>(cur, T / f.ax[a].n, f.ax[a], f.tw[a], none, s)) != hipSuccess) return err;
+    }
+  }
+  int64_t n_out = 1;
+  for (int a = 0; a < d; ++a) n_out *= f.yn[a];
+  if (n_out == 0) return hipSuccess;
   RowIO io{};
   io.y = f.y;
-  io.ys0 = f.ys0;
-  io.ys1 = f.ys1;
-  io.OH = f.OH;
-  io.OW = f.OW;
-  io.o0 = f.o0;
-  io.o1 = f.o1;
-  io.scale = 1.0f / ((float)P * (float)Q);
-  return rows_t<true, false, true>(f.A, f.OH, Q, f.twQ, io, s);
+  io.yc = f.ys[d - 1];
+  io.oc = f.o[d - 1];
+  io.ow = f.yn[d - 1];
+  io.scale = (float)(1.0 / (double)T);
+  if (d == 2) {
+    io.nb = 1;
+    io.OA = f.yn[0];
+    io.OB = 1;
+    io.oa = f.o[0];
+    io.ob = 0;
+    io.ya = f.ys[0];
+    io.yb = 0;
+  } else {
+    io.nb = f.ax[1].n;
+    io.OA = f.yn[0];
+    io.OB = f.yn[1];
+    io.oa = f.o[0];
+    io.ob = f.o[1];
+    io.ya = f.ys[0];
+    io.yb = f.ys[1];
+  }
+  return rows_t<true, false, true>(cur, (int64_t)io.OA * io.OB, f.ax[d - 1], f.tw[d - 1], io, s);
 }
 
 }  // namespace ttc

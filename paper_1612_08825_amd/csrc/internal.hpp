@@ -52,24 +52,34 @@ struct SepConv {
 bool separable_variant(int K);
 hipError_t launch_conv_separable(const SepConv& c, hipStream_t s);
 
-// FFT branch of 2-D FP32 convolution: x (H x W, strided) and k (KH x KW,
-// contiguous) zero-padded to P x Q (powers of two, <= kFftMaxN); twiddle
-// tables twP (P entries) and twQ (Q); A is P x Q, B and C are Q x P complex
-// scratch; the output y (OH x OW, strided) is full index n + (o0, o1).
+// FFT branch of 2-D and 3-D FP32 convolution: x (strided) and k (contiguous)
+// zero-padded to a volume n_0 x .. x n_{d-1} (d = rank, leading axis first)
+// whose extents are products of the stage radices (2, 3, 4, 5), at most
+// kFftMaxN each; per-axis twiddle tables tw[a] (n_a entries); A, B and C are
+// complex volumes of n_0 .. n_{d-1} points (scratch, the spectrum of x, the
+// spectrum of k); the output y (strided) is full index n + o.
 constexpr int kFftMaxN = 4096;
-struct FftConv {
-  const float* x;
-  int64_t xs0, xs1;
-  int H, W;
-  const float* k;
-  int KH, KW;
-  int P, Q;
-  float2 *twP, *twQ, *A, *B, *C;
-  float* y;
-  int64_t ys0, ys1;
-  int OH, OW, o0, o1;
+constexpr int kFftMaxStages = 12;
+struct FftAxis {
+  int n;
+  int n_stages;
+  int8_t radix[kFftMaxStages];  // n = product of radix[0 .. n_stages-1]
 };
-hipError_t launch_conv2d_fft(const FftConv& f, hipStream_t s);
+struct FftConv {
+  int rank;
+  const float* x;
+  int64_t xs[3];
+  int xn[3];
+  const float* k;
+  int kn[3];
+  FftAxis ax[3];
+  float2* tw[3];
+  float2 *A, *B, *C;
+  float* y;
+  int64_t ys[3];
+  int yn[3], o[3];
+};
+hipError_t launch_conv_fft(const FftConv& f, hipStream_t s);
 
 // Zero `bytes` (a multiple of 4) of device memory with a kernel (graph-safe).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);

@@ -312,44 +312,112 @@ extern "C" int tc_conv_nd_separable(const tc_tensor* x, const tc_tensor* u, cons
 namespace {
 
 struct FftLayout {
-  int P = 0, Q = 0;
-  size_t twP = 0, twQ = 0, A = 0, B = 0, C = 0, total = 0;
+  int rank = 0;
+  FftAxis ax[3] = {};
+  int64_t volume = 0;  // n_0 .. n_{d-1}
+  size_t tw[3] = {0, 0, 0}, A = 0, B = 0, C = 0, total = 0;
   int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
 };
 
 size_t fft_align(size_t v) { return (v + 255) / 256 * 256; }
 
-int pow2_at_least(int64_t n) {
-  int64_t p = 2;
-  while (p < n) p <<= 1;
-  return (int)p;
+// The smallest 2^a 3^b 5^c >= n (n <= kFftMaxN), with its stages: radix 4 while
+// two factors of 2 remain, a radix-2 stage for an odd one, then the 3s and 5s.
+FftAxis fft_axis(int64_t n) {
+  FftAxis ax{};
+  for (int64_t m = n < 1 ? 1 : n;; ++m) {
+    int64_t r = m;
+    int a = 0, b = 0, c = 0;
+    while (r % 2 == 0) r /= 2, ++a;
+    while (r % 3 == 0) r /= 3, ++b;
+    while (r % 5 == 0) r /= 5, ++c;
+    if (r != 1) continue;
+    ax.n = (int)m;
+    int st = 0;
+    for (int i = 0; i < a / 2; ++i) ax.radix[st++] = 4;
+    if (a % 2) ax.radix[st++] = 2;
+    for (int i = 0; i < b; ++i) ax.radix[st++] = 3;
+    for (int i = 0; i < c; ++i) ax.radix[st++] = 5;
+    ax.n_stages = st;
+    return ax;
+  }
 }
 
 int fft_layout(const tc_tensor* x, const tc_tensor* k, int32_t mode, FftLayout& L) {
   if (x->dtype != TC_F32 || k->dtype != TC_F32) return TC_EDTYPE;
-  if (x->ndim != 2 || k->ndim != 2) return TC_ESHAPE;
+  if (x->ndim != k->ndim || (x->ndim != 2 && x->ndim != 3)) return TC_ESHAPE;
   int st;
   if ((st = conv_geometry(x, k, mode, L.oshape, L.off)) != TC_OK) return st;
-  const int64_t fh = x->shape[0] + k->shape[0] - 1, fw = x->shape[1] + k->shape[1] - 1;
-  if (fh > kFftMaxN || fw > kFftMaxN) return TC_ESHAPE;
-  L.P = pow2_at_least(fh);
-  L.Q = pow2_at_least(fw);
+  L.rank = (int)x->ndim;
+  L.volume = 1;
+  int64_t n_min = kFftMaxN;
+  for (int a = 0; a < L.rank; ++a) {
+    const int64_t full = x->shape[a] + k->shape[a] - 1;
+    if (full > kFftMaxN) return TC_ESHAPE;
+    L.ax[a] = fft_axis(full);
+    L.volume *= L.ax[a].n;
+    n_min = std::min<int64_t>(n_min, L.ax[a].n);
+  }
+  // one work-group per row: at most 2^31 - 1 rows along any axis
+  if (L.volume / n_min > INT32_MAX) return TC_ESHAPE;
   size_t o = 0;
-  L.twP = o;
-  o += fft_align((size_t)L.P * sizeof(float2));
-  L.twQ = o;
-  o += fft_align((size_t)L.Q * sizeof(float2));
-  const size_t plane = fft_align((size_t)L.P * L.Q * sizeof(float2));
+  for (int a = 0; a < L.rank; ++a) {
+    L.tw[a] = o;
+    o += fft_align((size_t)L.ax[a].n * sizeof(float2));
+  }
+  const size_t vol = fft_align((size_t)L.volume * sizeof(float2));
   L.A = o;
-  L.B = o + plane;
-  L.C = o + 2 * plane;
-  L.total = o + 3 * plane;
+  L.B = o + vol;
+  L.C = o + 2 * vol;
+  L.total = o + 3 * vol;
   return TC_OK;
+}
+
+int conv_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws, size_t ws_bytes,
+             void* stream) {
+  int st;
+  if ((st = check_tensor(x, true)) != TC_OK) return st;
+  if ((st = check_tensor(k, true)) != TC_OK) return st;
+  if ((st = check_tensor(y, true)) != TC_OK) return st;
+  if (y->dtype != TC_F32) return TC_EDTYPE;
+  FftLayout L;
+  if ((st = fft_layout(x, k, mode, L)) != TC_OK) return st;
+  if (!is_contiguous(k) || y->ndim != x->ndim) return TC_ESHAPE;
+  for (int a = 0; a < L.rank; ++a)
+    if (y->shape[a] != L.oshape[a]) return TC_ESHAPE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (numel(y) == 0) return TC_OK;
+  if (numel(x) == 0 || numel(k) == 0) {
+    if (is_contiguous(y)) return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
+    return TC_ESHAPE;
+  }
+  if (!ws) return TC_EINVAL;
+  if (ws_bytes < L.total) return TC_ENOMEM;
+  char* w = static_cast<char*>(ws);
+  FftConv f{};
+  f.rank = L.rank;
+  f.x = static_cast<const float*>(x->data);
+  f.k = static_cast<const float*>(k->data);
+  f.y = static_cast<float*>(y->data);
+  for (int a = 0; a < L.rank; ++a) {
+    f.xs[a] = x->stride[a];
+    f.xn[a] = (int)x->shape[a];
+    f.kn[a] = (int)k->shape[a];
+    f.ax[a] = L.ax[a];
+    f.tw[a] = reinterpret_cast<float2*>(w + L.tw[a]);
+    f.ys[a] = y->stride[a];
+    f.yn[a] = (int)y->shape[a];
+    f.o[a] = (int)L.off[a];
+  }
+  f.A = reinterpret_cast<float2*>(w + L.A);
+  f.B = reinterpret_cast<float2*>(w + L.B);
+  f.C = reinterpret_cast<float2*>(w + L.C);
+  return hip_status(launch_conv_fft(f, s));
 }
 
 }  // namespace
 
-extern "C" int tc_conv2d_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes) {
+extern "C" int tc_conv_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes) {
   if (!x || !k || !ws_bytes) return TC_EINVAL;
   int st;
   if ((st = check_tensor(x, false)) != TC_OK) return st;
@@ -360,59 +428,33 @@ extern "C" int tc_conv2d_fft_workspace_size(const tc_tensor* x, const tc_tensor*
   return TC_OK;
 }
 
+extern "C" int tc_conv_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!x || !k || !y) return TC_EINVAL;
+  return conv_fft(x, k, mode, y, ws, ws_bytes, stream);
+}
+
+extern "C" int tc_conv2d_fft_workspace_size(const tc_tensor* x, const tc_tensor* k, int32_t mode, size_t* ws_bytes) {
+  if (!x || !k || !ws_bytes) return TC_EINVAL;
+  if (x->ndim != 2 || k->ndim != 2) return TC_ESHAPE;
+  return tc_conv_fft_workspace_size(x, k, mode, ws_bytes);
+}
+
 extern "C" int tc_conv2d_fft(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc_tensor* y, void* ws,
                              size_t ws_bytes, void* stream) {
-  int st;
-  if ((st = check_tensor(x, true)) != TC_OK) return st;
-  if ((st = check_tensor(k, true)) != TC_OK) return st;
-  if ((st = check_tensor(y, true)) != TC_OK) return st;
-  if (y->dtype != TC_F32) return TC_EDTYPE;
-  FftLayout L;
-  if ((st = fft_layout(x, k, mode, L)) != TC_OK) return st;
-  if (!is_contiguous(k) || y->ndim != 2) return TC_ESHAPE;
-  if (y->shape[0] != L.oshape[0] || y->shape[1] != L.oshape[1]) return TC_ESHAPE;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (numel(y) == 0) return TC_OK;
-  if (numel(x) == 0 || numel(k) == 0) {
-    if (y->stride[1] == 1 && y->stride[0] == y->shape[1])
-      return hip_status(launch_fill_zero(y->data, (size_t)numel(y) * 4, s));
-    return TC_ESHAPE;
-  }
-  if (!ws) return TC_EINVAL;
-  if (ws_bytes < L.total) return TC_ENOMEM;
-  char* w = static_cast<char*>(ws);
-  FftConv f{};
-  f.x = static_cast<const float*>(x->data);
-  f.xs0 = x->stride[0];
-  f.xs1 = x->stride[1];
-  f.H = (int)x->shape[0];
-  f.W = (int)x->shape[1];
-  f.k = static_cast<const float*>(k->data);
-  f.KH = (int)k->shape[0];
-  f.KW = (int)k->shape[1];
-  f.P = L.P;
-  f.Q = L.Q;
-  f.twP = reinterpret_cast<float2*>(w + L.twP);
-  f.twQ = reinterpret_cast<float2*>(w + L.twQ);
-  f.A = reinterpret_cast<float2*>(w + L.A);
-  f.B = reinterpret_cast<float2*>(w + L.B);
-  f.C = reinterpret_cast<float2*>(w + L.C);
-  f.y = static_cast<float*>(y->data);
-  f.ys0 = y->stride[0];
-  f.ys1 = y->stride[1];
-  f.OH = (int)y->shape[0];
-  f.OW = (int)y->shape[1];
-  f.o0 = (int)L.off[0];
-  f.o1 = (int)L.off[1];
-  return hip_status(launch_conv2d_fft(f, s));
+  if (!x || !k || !y) return TC_EINVAL;
+  if (x->ndim != 2 || k->ndim != 2) return TC_ESHAPE;
+  return conv_fft(x, k, mode, y, ws, ws_bytes, stream);
 }
 
 // ============================================================================ dispatcher
 namespace {
 
 // The kernel side from which the FFT branch beats the direct kernels on
-// MI355X (2048 x 2048 FP32 images, full mode, square kernels).
-constexpr int kFftThresholdDefault = 37;
+// MI355X (FP32, full mode, cubic kernels): 2048 x 2048 images, and 3-D
+// volumes of 64 x 256 x 256.
+constexpr int kFftThreshold2D = 27;
+constexpr int kFftThreshold3D = 9;
 // Relative tolerance of the rank-one test the dispatcher applies to a host copy
 // of a square FP32 kernel (max |k - u v^T| <= tol * max |k|).
 constexpr double kSeparableTol = 0x1p-20;
@@ -473,9 +515,9 @@ extern "C" int tc_conv_nd_ex(const tc_tensor* x, const tc_tensor* k, int32_t mod
     }
     int64_t kmax = 0;
     for (int d = 0; d < k->ndim; ++d) kmax = std::max(kmax, k->shape[d]);
-    const int thr = o.fft_threshold > 0 ? o.fft_threshold : kFftThresholdDefault;
+    const int thr = o.fft_threshold > 0 ? o.fft_threshold : (x->ndim == 3 ? kFftThreshold3D : kFftThreshold2D);
     const bool want = o.method == TC_CONV_FFT || (ok && kmax >= thr && o.workspace && o.workspace_bytes >= L.total);
-    if (want) return tc_conv2d_fft(x, k, mode, y, o.workspace, o.workspace_bytes, stream);
+    if (want) return conv_fft(x, k, mode, y, o.workspace, o.workspace_bytes, stream);
   }
   // separable square F32 kernels, when the caller lent a host copy to test:
   // the factors travel by value in the kernel arguments

@@ -250,3 +250,47 @@ def test_ttc_tuning_defaults_and_rejections(lib):
         assert not h.value
     # re-planning needs a plan and a valid batch
     assert lib.tc_ttc_plan_reset(None, arr, 1) == L.TC_EINVAL
+
+
+def _fft_axis_extent(n):
+    m = max(1, n)
+    while True:
+        r = m
+        for p in (2, 3, 5):
+            while r % p == 0:
+                r //= p
+        if r == 1:
+            return m
+        m += 1
+
+
+def test_fft_workspace_follows_the_padding_rule(lib):
+    """tc_conv_fft_workspace_size: one twiddle table per axis and three complex
+    volumes, every axis padded to the smallest 2^a 3^b 5^c holding the full
+    output (at most 4096), 256-byte aligned pieces."""
+    al = lambda v: (v + 255) // 256 * 256
+    cases = [((2048, 2048), (37, 37)), ((37, 50), (5, 7)), ((64, 256, 256), (15, 15, 15)), ((1, 1), (1, 1)),
+             ((9, 20, 17), (3, 5, 4)), ((4000, 7), (97, 1))]
+    for xs, ks in cases:
+        n = [_fft_axis_extent(a + b - 1) for a, b in zip(xs, ks)]
+        vol = 1
+        for v in n:
+            vol *= v
+        want = sum(al(v * 8) for v in n) + 3 * al(vol * 8)
+        got = C.c_size_t(0)
+        x, k = _desc(xs, L.TC_F32), _desc(ks, L.TC_F32)
+        assert lib.tc_conv_fft_workspace_size(C.byref(x), C.byref(k), L.TC_FULL, C.byref(got)) == L.TC_OK
+        assert got.value == want, (xs, ks, n, got.value, want)
+        if len(xs) == 2:
+            g2 = C.c_size_t(0)
+            assert lib.tc_conv2d_fft_workspace_size(C.byref(x), C.byref(k), L.TC_FULL, C.byref(g2)) == L.TC_OK
+            assert g2.value == want
+        else:
+            assert lib.tc_conv2d_fft_workspace_size(C.byref(x), C.byref(k), L.TC_FULL, C.byref(got)) == L.TC_ESHAPE
+    assert _fft_axis_extent(2084) == 2160 and _fft_axis_extent(4097) == 4320
+    bad = [((1, 4090), (1, 8), L.TC_F32), ((2, 2, 2, 2), (1, 1, 1, 1), L.TC_F32), ((4, 5, 6), (3, 3), L.TC_F32)]
+    for xs, ks, dt in bad:
+        assert lib.tc_conv_fft_workspace_size(C.byref(_desc(xs, dt)), C.byref(_desc(ks, dt)), L.TC_FULL,
+                                              C.byref(C.c_size_t(0))) == L.TC_ESHAPE, (xs, ks)
+    assert lib.tc_conv_fft_workspace_size(C.byref(_desc((8, 8), L.TC_F16)), C.byref(_desc((3, 3), L.TC_F32)),
+                                          L.TC_FULL, C.byref(C.c_size_t(0))) == L.TC_EDTYPE
