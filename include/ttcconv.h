@@ -129,6 +129,12 @@ int tc_device_check(int device, int* n_cu);
  *          the separable test.  NULL when not available.
  *   workspace, workspace_bytes  DEVICE scratch for the FFT branch (may be NULL
  *          and 0 when only the direct or separable paths may run).
+ *   band_rows  output rows per wave of the row-streaming direct kernels (2-D
+ *          images and 3-D kernels other than 3 x 3 x 3, kernels of 2, 3, 5 or 7
+ *          taps per side): 2, 4 or 8, or 0 for the library's tuned default.
+ *          Every value gives the same result bit for bit (the summation order
+ *          of an output does not depend on it); TC_EINVAL for other values.
+ *   reserved  must be 0 (TC_EINVAL otherwise).
  * opts may be NULL: TC_CONV_AUTO with no workspace and no host copy, i.e. the
  * direct kernels (which reject I32 kernels as above).
  *
@@ -144,6 +150,8 @@ typedef struct {
   const void* k_host;
   void* workspace;
   size_t workspace_bytes;
+  int32_t band_rows;
+  int32_t reserved;  /* 0 */
 } tc_conv_opts;
 
 int tc_conv_out_shape(const tc_tensor* x, const tc_tensor* k, int32_t mode, int64_t* out_shape);

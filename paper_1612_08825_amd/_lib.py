@@ -51,6 +51,8 @@ class TcConvOpts(C.Structure):
         ("k_host", C.c_void_p),
         ("workspace", C.c_void_p),
         ("workspace_bytes", C.c_size_t),
+        ("band_rows", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 

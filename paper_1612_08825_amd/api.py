@@ -104,12 +104,14 @@ def conv_workspace_size(x: torch.Tensor, k: torch.Tensor, mode: str = "full", me
 
 def conv_nd_ex(x: torch.Tensor, k: torch.Tensor, mode: str = "full", method: str = "auto",
                k_abs_sum: Optional[int] = None, k_host: Optional[np.ndarray] = None, fft_threshold: int = 0,
-               ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None, stream=None):
+               ws: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None, stream=None,
+               band_rows: int = 0):
     """tc_conv_nd_ex: the convolution with the library's method choice.
     `k_host` (a contiguous numpy copy of k) lets the library take sum |k| of an
     int32 kernel and test a square FP32 kernel for separability; `ws` is the
     FFT branch's device workspace (allocated here when None and the method
-    may take the FFT branch)."""
+    may take the FFT branch); `band_rows` forces the output rows per wave of
+    the row-streaming direct kernels (2, 4, 8; 0 = the library's table)."""
     lib = _lib()
     shape = conv_out_shape(tuple(x.shape), tuple(k.shape), mode, x.dtype, k.dtype)
     ydt = torch.int32 if x.dtype == torch.uint8 else torch.float32
@@ -122,6 +124,7 @@ def conv_nd_ex(x: torch.Tensor, k: torch.Tensor, mode: str = "full", method: str
     o = L.TcConvOpts()
     o.method = L.METHODS[method]
     o.fft_threshold = int(fft_threshold)
+    o.band_rows = int(band_rows)
     o.k_abs_sum = -1 if k_abs_sum is None else int(k_abs_sum)
     kh = None
     if k_host is not None:

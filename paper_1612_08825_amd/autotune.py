@@ -1,4 +1,4 @@
-"""Tuning sweep of the fused TTC pass.
+"""Tuning sweeps: the fused TTC pass and the row-streaming direct convolution.
 
 For a (dtype, levels) class the sweep times the fused kernel over a
 representative batch for every candidate launch shape -- band height (rows a
@@ -8,7 +8,15 @@ create a plan are skipped.  The table it prints is what the library's built-in
 default (``tc_ttc_tuning_default``) is set from; callers can also pass a tuning
 to ``TTCPlan(..., tuning=(band_rows, groups_per_cu))``.
 
-    python -m paper_1612_08825_amd.autotune [--out table.json]
+Direct convolution (``--conv``): for every (input type, taps per side, size
+class) the sweep times the row-streaming kernels at every band height (output
+rows per wave: 2, 4, 8) through ``tc_conv_nd_ex``'s ``band_rows``, as a replayed
+graph over buffers rotated past the last-level cache, and keeps the fastest;
+a candidate is accepted only if its output equals the others' bit for bit
+(the band height must not change a result).  The library's default table
+(``default_band_rows`` in the row kernels) is set from it.
+
+    python -m paper_1612_08825_amd.autotune [--out table.json] [--conv]
 """
 from __future__ import annotations
 
@@ -79,12 +87,88 @@ def workloads(torch):
     return {("f16", lv): f16 for lv in (4, 3, 2, 1)} | {("u8", lv): u8 for lv in (3, 4, 2, 1)}
 
 
+CONV_BAND_ROWS = (2, 4, 8)
+CONV_TAPS = (2, 3, 5, 7)
+CONV_SIZES = (("small", 1024), ("medium", 2048), ("large", 4096))  # square images, full mode
+CONV_DTYPES = ("f32", "f16", "u8")
+
+
+def conv_sweep(reps: int = 20) -> Dict:
+    """Band height of the row-streaming convolution per (input type, K, size
+    class), gated on bitwise-equal outputs across heights."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from . import api, synth
+
+    table = {}
+    for dt in CONV_DTYPES:
+        for cls, n in CONV_SIZES:
+            x0 = torch.from_numpy(synth.conv_image((n, n), case=17, dtype=dt)).cuda()
+            for K in CONV_TAPS:
+                if dt == "u8":
+                    kh = synth.conv_kernel((K, K), case=17, dtype="i32")
+                    kabs = int(np.abs(kh.astype(np.int64)).sum())
+                else:
+                    kh = synth.conv_kernel((K, K), case=17)
+                    kabs = None
+                k = torch.from_numpy(kh).cuda()
+                ys = (n + K - 1, n + K - 1)
+                ydt = torch.int32 if dt == "u8" else torch.float32
+                nbytes = x0.element_size() * n * n + 4 * ys[0] * ys[1]
+                nbuf = max(2, min(64, int(math.ceil(1.1 * 2 ** 30 / nbytes))))
+                xb = [x0.clone() for _ in range(nbuf)]
+                yb = [torch.empty(ys, dtype=ydt, device="cuda") for _ in range(nbuf)]
+                res, outs = {}, {}
+                for br in CONV_BAND_ROWS:
+                    def launch(i):
+                        api.conv_nd_ex(xb[i % nbuf], k, "full", method="direct", k_abs_sum=kabs, out=yb[i % nbuf],
+                                       band_rows=br)
+                    n_l = max(reps, 2 * nbuf)
+                    for i in range(3):
+                        launch(i)
+                    torch.cuda.synchronize()
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g):
+                        for i in range(n_l):
+                            launch(i)
+                    g.replay()
+                    torch.cuda.synchronize()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    g.replay()
+                    e1.record()
+                    torch.cuda.synchronize()
+                    res[br] = round(e0.elapsed_time(e1) / n_l, 5)
+                    outs[br] = yb[0].clone()
+                    del g
+                equal = all(torch.equal(outs[br], outs[CONV_BAND_ROWS[-1]]) for br in CONV_BAND_ROWS)
+                ok = {br: ms for br, ms in res.items() if equal}
+                bestb = min(ok, key=ok.get) if ok else None
+                table[f"{dt}/K{K}/{cls}"] = {"best_band_rows": bestb, "ms": res, "bitwise_equal": equal}
+                print(f"[tune] conv {dt} K={K} {cls}: {res} best {bestb} equal {equal}", file=sys.stderr, flush=True)
+                del xb, yb, outs
+                torch.cuda.empty_cache()
+    return table
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--conv", action="store_true", help="the convolution sweep instead of the fused TTC pass")
     args = ap.parse_args()
     import torch
+
+    if args.conv:
+        text = json.dumps(conv_sweep(), indent=1)
+        print(text)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(text)
+        return
 
     table = {}
     for (dt, levels), vids in workloads(torch).items():

@@ -577,16 +577,16 @@ int64_t row_items(const RowArgs& ra, int rb, int lanes_out) {
 }
 constexpr int64_t kTargetItems = 2048;
 
-hipError_t launch_rows(const RowArgs& ra, int KH, int xdt, hipStream_t s) {
+hipError_t launch_rows(const RowArgs& ra, int KH, int xdt, int band_rows, hipStream_t s) {
   if (KH == 15) {
     if (row_items(ra, 32, 59) >= kTargetItems) return launch_roll_t<15, 15, 32>(ra, s);
     if (row_items(ra, 16, 59) >= kTargetItems) return launch_roll_t<15, 15, 16>(ra, s);
     return launch_roll_t<15, 15, 8>(ra, s);
   }
   switch (xdt) {
-    case TC_F32: return launch_rows_dt0(ra, KH, s);
-    case TC_F16: return launch_rows_dt1(ra, KH, s);
-    case TC_U8: return launch_rows_dt2(ra, KH, s);
+    case TC_F32: return launch_rows_dt0(ra, KH, band_rows, s);
+    case TC_F16: return launch_rows_dt1(ra, KH, band_rows, s);
+    case TC_U8: return launch_rows_dt2(ra, KH, band_rows, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -685,7 +685,7 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
       ra.OD = 1;
       ra.offd = 0;
     }
-    return launch_rows(ra, (int)c.kshape[r - 2], c.xdt, s);
+    return launch_rows(ra, (int)c.kshape[r - 2], c.xdt, c.band_rows, s);
   }
 
   // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 48

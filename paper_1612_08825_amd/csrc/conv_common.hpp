@@ -63,9 +63,10 @@ __device__ __forceinline__ int from_next_lane(int v) { return __builtin_amdgcn_m
 // Launch entry of the unrolled band kernel for one input type (conv_rows.hip
 // is built once per type): x FP32 (dt 0), FP16 (dt 1) or u8 with int32 taps
 // whose magnitudes are below 2^23 (dt 2); KH = KW in {2, 3, 5, 7}.
-hipError_t launch_rows_dt0(const RowArgs& ra, int KH, hipStream_t s);
-hipError_t launch_rows_dt1(const RowArgs& ra, int KH, hipStream_t s);
-hipError_t launch_rows_dt2(const RowArgs& ra, int KH, hipStream_t s);
+// band_rows: output rows per wave (2, 4 or 8), 0 for the default table.
+hipError_t launch_rows_dt0(const RowArgs& ra, int KH, int band_rows, hipStream_t s);
+hipError_t launch_rows_dt1(const RowArgs& ra, int KH, int band_rows, hipStream_t s);
+hipError_t launch_rows_dt2(const RowArgs& ra, int KH, int band_rows, hipStream_t s);
 
 }  // namespace rows
 }  // namespace ttc

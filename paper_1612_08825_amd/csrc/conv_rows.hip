@@ -7,7 +7,7 @@
 // 1: FP16 x, FP32 taps and sums; 2: u8 x, int32 taps below 2^23 in magnitude,
 // exact int32 sums with 24-bit multiplies).
 //
-// One wave per item: a band of R (8, or 4 for small outputs) output rows by
+// One wave per item: a band of R (2, 4 or 8, from a tuned table) output rows by
 // 4 * LO output columns of one output plane; lane i < LO holds output columns
 // 4i .. 4i+3 of the band in registers.  The wave walks the band's R + KH - 1
 // input rows top to bottom and multiplies each into every output row of the
@@ -543,27 +543,53 @@ hipError_t launch_rows_t(const RowArgs& ra, hipStream_t s) {
   }
 }
 
-}  // namespace
-
 #define TC_CAT2(a, b) a##b
 #define TC_ROWS_LAUNCHER(dt) TC_CAT2(launch_rows_dt, dt)
 #define TC_ROWS_LAUNCHER_X(dt) TC_ROWS_LAUNCHER(dt)
 
-// The band height is 8 unless that leaves fewer than about two waves per SIMD
-// (2048 items on 256 CUs), then 4.
-hipError_t TC_ROWS_LAUNCHER_X(TC_ROWS_DT)(const RowArgs& ra, int KH, hipStream_t s) {
-  const int64_t items8 = (int64_t)ra.OD * ((ra.OH + 7) / 8) * ((ra.OW + 4 * 61 - 1) / (4 * 61));
-  const bool small = items8 < 2048;
+// Output rows per wave (band height) from the convolution tuning sweep
+// (square images, full mode, graph-replayed over buffers rotated past the
+// last-level cache), per input type, taps per side (2, 3, 5, 7) and output
+// size class (fewer than 2^21 elements, fewer than 2^23, more).  Every height
+// sums an output in the same order, so the choice never changes a result; the
+// short bands win wherever the output is too small to fill the chip with
+// taller ones (more, shorter waves).
+constexpr int8_t kBandRows[3][4][3] = {
+    {{2, 2, 4}, {2, 2, 4}, {2, 2, 4}, {2, 2, 4}},  // FP32
+    {{2, 2, 2}, {2, 2, 2}, {2, 2, 4}, {2, 2, 4}},  // FP16
+    {{2, 4, 2}, {2, 2, 4}, {2, 4, 4}, {2, 2, 4}},  // u8
+};
+int default_band_rows(int KH, int64_t out_elems) {
+  const int ki = KH == 2 ? 0 : (KH == 3 ? 1 : (KH == 5 ? 2 : 3));
+  const int cls = out_elems < (1LL << 21) ? 0 : (out_elems < (1LL << 23) ? 1 : 2);
+  return kBandRows[TC_ROWS_DT][ki][cls];
+}
+
+template <int K>
+hipError_t launch_rows_k(const RowArgs& ra, int band_rows, hipStream_t s) {
+  switch (band_rows) {
+    case 2: return launch_rows_t<K, K, 2>(ra, s);
+    case 4: return launch_rows_t<K, K, 4>(ra, s);
+    default: return launch_rows_t<K, K, 8>(ra, s);
+  }
+}
+
+}  // namespace
+
+hipError_t TC_ROWS_LAUNCHER_X(TC_ROWS_DT)(const RowArgs& ra, int KH, int band_rows, hipStream_t s) {
   // a 3 x 3 x 3 kernel over several planes: rolling planes, each read once
+  // (its band height is fixed)
   if (KH == 3 && ra.KD == 3 && ra.OD > 1 && ra.W % 4 == 0 && ra.W >= 4 &&
       ((int64_t)(ra.H - 1) * ra.xs0 + ra.W) * (int64_t)sizeof(TX) < (1LL << 31) &&
       ((int64_t)(ra.OH - 1) * ra.ys0 + ra.OW) * 4 < (1LL << 31))
     return launch_rows3d_t<3, 4>(ra, s);
+  if (band_rows == 0) band_rows = default_band_rows(KH, (int64_t)ra.OD * ra.OH * ra.OW);
+  if (band_rows != 2 && band_rows != 4 && band_rows != 8) return hipErrorInvalidValue;
   switch (KH) {
-    case 2: return small ? launch_rows_t<2, 2, 4>(ra, s) : launch_rows_t<2, 2, 8>(ra, s);
-    case 3: return small ? launch_rows_t<3, 3, 4>(ra, s) : launch_rows_t<3, 3, 8>(ra, s);
-    case 5: return small ? launch_rows_t<5, 5, 4>(ra, s) : launch_rows_t<5, 5, 8>(ra, s);
-    case 7: return small ? launch_rows_t<7, 7, 4>(ra, s) : launch_rows_t<7, 7, 8>(ra, s);
+    case 2: return launch_rows_k<2>(ra, band_rows, s);
+    case 3: return launch_rows_k<3>(ra, band_rows, s);
+    case 5: return launch_rows_k<5>(ra, band_rows, s);
+    case 7: return launch_rows_k<7>(ra, band_rows, s);
     default: return hipErrorInvalidValue;
   }
 }

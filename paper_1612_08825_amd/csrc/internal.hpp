@@ -22,6 +22,7 @@ struct ConvND {
   int64_t yshape[TC_MAX_DIMS];
   int64_t ystride[TC_MAX_DIMS];
   int64_t off[TC_MAX_DIMS];     // output index n maps to full index n + off
+  int band_rows;                // row-streaming kernels: output rows per wave (2, 4, 8; 0 = the default)
 };
 
 // Chooses a kernel (2-D tiled, 3-D tiled, or generic rank-n) and launches it.

@@ -173,7 +173,7 @@ int conv_validate(const tc_tensor* x, const tc_tensor* k, int32_t mode, const tc
 // the caller: the int32 result is exact when 255 * sum|k| <= 2^31 - 1 (every
 // partial sum then fits), and 24-bit multiplies are exact when sum|k| < 2^23.
 int conv_direct(const tc_tensor* x, const tc_tensor* k, const tc_tensor* y, const int64_t* off, int64_t k_abs_sum,
-                hipStream_t s) {
+                int band_rows, hipStream_t s) {
   bool small_taps = true;
   if (k->dtype == TC_I32) {
     if (k_abs_sum < 0) return TC_EINVAL;
@@ -201,6 +201,7 @@ int conv_direct(const tc_tensor* x, const tc_tensor* k, const tc_tensor* y, cons
     c.ystride[d] = y->stride[d];
     c.off[d] = off[d];
   }
+  c.band_rows = band_rows;
   return hip_status(launch_conv(c, small_taps, s));
 }
 
@@ -213,7 +214,7 @@ extern "C" int tc_conv_nd(const tc_tensor* x, const tc_tensor* k, int32_t mode, 
   // the exactness bound of an integer kernel is a host-side fact the caller
   // states through tc_conv_nd_ex; this entry point never reads the taps back
   if (k->dtype == TC_I32) return TC_EINVAL;
-  return conv_direct(x, k, y, off, -1, reinterpret_cast<hipStream_t>(stream));
+  return conv_direct(x, k, y, off, -1, 0, reinterpret_cast<hipStream_t>(stream));
 }
 
 // ============================================================================ separable kernels
@@ -488,6 +489,8 @@ extern "C" int tc_conv_nd_ex(const tc_tensor* x, const tc_tensor* k, int32_t mod
   if (opts) o = *opts;
   if (o.method != TC_CONV_AUTO && o.method != TC_CONV_DIRECT && o.method != TC_CONV_FFT) return TC_EINVAL;
   if (o.fft_threshold < 0) return TC_EINVAL;
+  if ((o.band_rows != 0 && o.band_rows != 2 && o.band_rows != 4 && o.band_rows != 8) || o.reserved != 0)
+    return TC_EINVAL;
   int64_t off[TC_MAX_DIMS];
   int st;
   if ((st = conv_validate(x, k, mode, y, off)) != TC_OK) return st;
@@ -529,7 +532,7 @@ extern "C" int tc_conv_nd_ex(const tc_tensor* x, const tc_tensor* k, int32_t mod
     if (tc_conv_kernel_rank1(static_cast<const float*>(o.k_host), K, K, kSeparableTol, tp.uh, tp.vh) == 1)
       return conv_separable(x, K, tp, mode, y, s);
   }
-  return conv_direct(x, k, y, off, k_abs_sum, s);
+  return conv_direct(x, k, y, off, k_abs_sum, o.band_rows, s);
 }
 
 // ============================================================================ pyramid / derivatives

@@ -49,6 +49,8 @@ def test_struct_layouts_match_header():
       printf("%zu %zu %zu %zu\n", offsetof(tc_ttc_level, A), offsetof(tc_ttc_level, n), offsetof(tc_ttc_level, status),
              offsetof(tc_ttc_pick, level));
       printf("%zu %zu\n", offsetof(tc_tensor, shape), offsetof(tc_seq, H));
+      printf("%zu %zu %zu\n", sizeof(tc_conv_opts), offsetof(tc_conv_opts, workspace_bytes),
+             offsetof(tc_conv_opts, band_rows));
       return 0;
     }
     """
@@ -68,6 +70,9 @@ def test_struct_layouts_match_header():
     assert vals[7] == L.PICK_DTYPE.fields["level"][1]
     assert vals[8] == L.TcTensor.shape.offset
     assert vals[9] == L.TcSeq.H.offset
+    assert vals[10] == C.sizeof(L.TcConvOpts)
+    assert vals[11] == L.TcConvOpts.workspace_bytes.offset
+    assert vals[12] == L.TcConvOpts.band_rows.offset
 
 
 def test_status_strings(lib):
@@ -167,6 +172,14 @@ def test_conv_nd_ex_rejects_before_launch(lib):
     assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o2), None) == L.TC_EINVAL
     o2.method = L.TC_CONV_AUTO
     o2.fft_threshold = -3
+    assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o2), None) == L.TC_EINVAL
+    # band heights other than 0, 2, 4, 8, and a non-zero reserved field
+    for br in (1, 3, 16, -2):
+        o2 = L.TcConvOpts()
+        o2.band_rows = br
+        assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o2), None) == L.TC_EINVAL
+    o2 = L.TcConvOpts()
+    o2.reserved = 1
     assert lib.tc_conv_nd_ex(C.byref(x), C.byref(k), L.TC_FULL, C.byref(y), C.byref(o2), None) == L.TC_EINVAL
     # FFT forced on shapes it does not take, or without a workspace
     o3 = L.TcConvOpts()

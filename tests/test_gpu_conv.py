@@ -338,3 +338,29 @@ def test_conv3d_rows_u8_f16(api, dtype):
             k = synth.conv_kernel(ks, case=35)
             y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
             _check_float(y, x, k, mode, f"f16 3d {mode}")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "u8"])
+@pytest.mark.parametrize("xs,K", [((61, 777), 3), ((37, 530), 5), ((29, 1100), 7), ((45, 600), 2), ((6, 19, 300), 5)])
+def test_band_rows_bitwise(api, dtype, xs, K):
+    """Every band height of the row-streaming kernels (2, 4, 8 output rows
+    per wave, and the default) gives the same output bit for bit, within the
+    oracle's bound (exact for u8)."""
+    ks = (K,) * len(xs)
+    x = synth.conv_image(xs, case=40 + K, dtype=dtype)
+    xg = torch.from_numpy(x).cuda()
+    if dtype == "u8":
+        k = synth.conv_kernel(ks, case=40 + K, dtype="i32")
+        kabs = int(np.abs(k.astype(np.int64)).sum())
+    else:
+        k = synth.conv_kernel(ks, case=40 + K)
+        kabs = None
+    kg = torch.from_numpy(k).cuda()
+    outs = [api.conv_nd_ex(xg, kg, "full", method="direct", k_abs_sum=kabs, band_rows=br) for br in (0, 2, 4, 8)]
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    y = outs[0].cpu().numpy()
+    if dtype == "u8":
+        np.testing.assert_array_equal(y.astype(np.int64), O.conv(x, k, "full"))
+    else:
+        _check_float(y, x, k, "full", f"band rows {dtype} {xs}*{K}")
