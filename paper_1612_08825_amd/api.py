@@ -190,7 +190,7 @@ SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
 # MI355X (FP32, full mode, cubic kernels; bench.py's crossover sweeps): 2048 x
 # 2048 images, and 64 x 256 x 256 volumes.  The library's dispatcher
 # (tc_conv_nd_ex) uses the same values.
-FFT_THRESHOLD = 27
+FFT_THRESHOLD = 19
 FFT_THRESHOLD_3D = 9
 FFT_MAX_N = 4096
 

@@ -166,11 +166,23 @@ struct RowIO {
 
 // A work-group transforms nr = max(1, kFftMaxN / N) consecutive rows (rows
 // 0 .. n_rows - 1 in all); dynamic LDS: nr N points, then N / 2 twiddles.
-template <bool INV, bool IN_REAL, bool OUT_REAL>
+//
+// HALF (the last axis, real data): the row is real and 2N long; it is
+// transformed as N complex points z[m] = x[2m] + i x[2m+1] and kept as its
+// N + 1 non-negative frequencies (a stored row is N + 1 long).  Forward (with
+// IN_REAL), after the N-point transform Z: X[k] = E + W^k O for k <= N, with
+// E = (Z[k] + conj Z[N-k]) / 2, O = -i (Z[k] - conj Z[N-k]) / 2 (the
+// transforms of the even and the odd samples), W = exp(-2 pi i / 2N).
+// Inverse (with OUT_REAL), before the transform: Z[k] = E + i O with
+// E = (X[k] + conj X[N-k]) / 2, O = W^-k (X[k] - conj X[N-k]) / 2, and the
+// inverse of Z holds N (x[2m] + i x[2m+1]).  tw is then the 2N-point table:
+// the N-point transform reads every second entry.
+template <bool INV, bool IN_REAL, bool OUT_REAL, bool HALF>
 __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ data, FftAxis ax,
                                                         const float2* __restrict__ tw, int64_t n_rows, RowIO io) {
   extern __shared__ float2 lds[];
   const int N = ax.n;
+  const int ld = HALF ? N + 1 : N;  // stored row length
   const int nr = N >= kFftMaxN ? 1 : kFftMaxN / N;
   float2* buf = lds;
   float2* twl = lds + nr * N;
@@ -192,18 +204,43 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
       any |= a < io.ea && b < io.eb;
     }
     if (!any) {
-      for (int64_t e = tid; e < (int64_t)nrow * N; e += kFftThreads) data[g0 * N + e] = make_float2(0.f, 0.f);
+      for (int64_t e = tid; e < (int64_t)nrow * ld; e += kFftThreads) data[g0 * ld + e] = make_float2(0.f, 0.f);
       return;
     }
     for (int e = tid; e < nr * N; e += kFftThreads) {
       const int i = e / N, c = e - i * N;
-      float v = 0.f;
+      float2 v = make_float2(0.f, 0.f);
       if (i < nrow) {
         const int64_t r = row_of(i);
         const int64_t a = r / io.nb, b = r - a * io.nb;
-        if (a < io.ea && b < io.eb && c < io.w_in) v = io.src[a * io.sa + b * io.sb + (int64_t)c * io.s_in];
+        if (a < io.ea && b < io.eb) {
+          const float* sr = io.src + a * io.sa + b * io.sb;
+          if (HALF) {
+            if (2 * c < io.w_in) v.x = sr[(int64_t)(2 * c) * io.s_in];
+            if (2 * c + 1 < io.w_in) v.y = sr[(int64_t)(2 * c + 1) * io.s_in];
+          } else if (c < io.w_in) {
+            v.x = sr[(int64_t)c * io.s_in];
+          }
+        }
       }
-      buf[e] = make_float2(v, 0.f);
+      buf[e] = v;
+    }
+  } else if (HALF) {
+    // the N + 1 stored frequencies of each row -> Z (the inverse's input)
+    for (int e = tid; e < nr * N; e += kFftThreads) {
+      const int i = e / N, k = e - i * N;
+      float2 z = make_float2(0.f, 0.f);
+      if (i < nrow) {
+        const float2* row = data + row_of(i) * ld;
+        const float2 xk = row[k], xc = row[N - k];
+        const float2 ev = make_float2(0.5f * (xk.x + xc.x), 0.5f * (xk.y - xc.y));
+        const float2 d = make_float2(0.5f * (xk.x - xc.x), 0.5f * (xk.y + xc.y));  // (X[k] - conj X[N-k]) / 2
+        float2 w = tw[k];
+        w.y = -w.y;  // W^-k
+        const float2 od = cmul(w, d);
+        z = make_float2(ev.x - od.y, ev.y + od.x);  // E + i O
+      }
+      buf[e] = z;
     }
   } else {
     for (int e = tid; e < nr * N; e += kFftThreads) {
@@ -211,7 +248,7 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
       buf[e] = i < nrow ? data[row_of(i) * N + c] : make_float2(0.f, 0.f);
     }
   }
-  for (int i = tid; i < (N >> 1); i += kFftThreads) twl[i] = tw[i];
+  for (int i = tid; i < (N >> 1); i += kFftThreads) twl[i] = tw[HALF ? 2 * i : i];
   __syncthreads();
   // the stage list runs radix 4, then 2, then 3, then 5: one loop per radix
   // (a switch over the radix inside one loop costs twice the registers)
@@ -224,7 +261,28 @@ __global__ __launch_bounds__(kFftThreads) void fft_rows(float2* __restrict__ dat
     for (int i = 0; i < nrow; ++i) {
       const int64_t g = g0 + i;
       float* yr = io.y + (g / io.OB) * io.ya + (g % io.OB) * io.yb;
-      for (int c = tid; c < io.ow; c += kFftThreads) yr[(int64_t)c * io.yc] = buf[i * N + io.oc + c].x * io.scale;
+      for (int c = tid; c < io.ow; c += kFftThreads) {
+        const int n = io.oc + c;
+        float v;
+        if (HALF) {
+          const float2 z = buf[i * N + (n >> 1)];
+          v = (n & 1) ? z.y : z.x;
+        } else {
+          v = buf[i * N + n].x;
+        }
+        yr[(int64_t)c * io.yc] = v * io.scale;
+      }
+    }
+  } else if (HALF) {
+    // the N + 1 non-negative frequencies of each real row
+    for (int e = tid; e < nrow * ld; e += kFftThreads) {
+      const int i = e / ld, k = e - i * ld;
+      const float2 zk = buf[i * N + (k == N ? 0 : k)], zc = buf[i * N + (k == 0 ? 0 : N - k)];
+      const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y - zc.y));
+      const float2 d = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y + zc.y));  // (Z[k] - conj Z[N-k]) / 2
+      const float2 od = make_float2(d.y, -d.x);                                    // -i d
+      const float2 wo = cmul(tw[k], od);
+      data[row_of(i) * ld + k] = make_float2(ev.x + wo.x, ev.y + wo.y);
     }
   } else {
     for (int e = tid; e < nrow * N; e += kFftThreads) {
@@ -261,14 +319,14 @@ __global__ __launch_bounds__(256) void mul_c(float2* __restrict__ a, const float
     a[i] = cmul(a[i], b[i]);
 }
 
-template <bool INV, bool IN_REAL, bool OUT_REAL>
+template <bool INV, bool IN_REAL, bool OUT_REAL, bool HALF = false>
 hipError_t rows_t(float2* d, int64_t n_rows, const FftAxis& ax, const float2* tw, const RowIO& io, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   const int N = ax.n;
   const int nr = N >= kFftMaxN ? 1 : kFftMaxN / N;
   const size_t lds = ((size_t)nr * N + (size_t)(N >> 1)) * sizeof(float2);
-  hipLaunchKernelGGL((fft_rows<INV, IN_REAL, OUT_REAL>), dim3((unsigned)((n_rows + nr - 1) / nr)), dim3(kFftThreads),
-                     lds, s, d, ax, tw, n_rows, io);
+  hipLaunchKernelGGL((fft_rows<INV, IN_REAL, OUT_REAL, HALF>), dim3((unsigned)((n_rows + nr - 1) / nr)),
+                     dim3(kFftThreads), lds, s, d, ax, tw, n_rows, io);
   return hipGetLastError();
 }
 
@@ -279,14 +337,26 @@ hipError_t transpose(const float2* src, int64_t R, int64_t C, float2* dst, hipSt
   return hipGetLastError();
 }
 
+// Stored extents of the spectrum: n_a for every axis but the last, whose
+// real transform keeps its n / 2 + 1 non-negative frequencies (the axis plan
+// of the last axis is for the half length).
+void stored_extents(const FftConv& f, int64_t (&ext)[3], int64_t& T) {
+  T = 1;
+  for (int a = 0; a < f.rank; ++a) {
+    ext[a] = a == f.rank - 1 ? (int64_t)f.ax[a].n + 1 : f.ax[a].n;
+    T *= ext[a];
+  }
+}
+
 // The forward transform of a real array (extents e[], strides st[], leading
 // axis first) zero-padded to the volume; the spectrum ends in `out`, in the
-// order (n_1, .., n_{d-1}, n_0); `tmp` is scratch of the same size.
+// order (n_1, .., n_{d-1}, n_0) with the last axis halved; `tmp` is scratch of
+// the same size.
 hipError_t forward(const FftConv& f, const float* src, const int64_t* st, const int* e, float2* tmp, float2* out,
                    hipStream_t s) {
   const int d = f.rank;
-  int64_t T = 1;
-  for (int a = 0; a < d; ++a) T *= f.ax[a].n;
+  int64_t ext[3], T;
+  stored_extents(f, ext, T);
   RowIO io{};
   io.src = src;
   io.s_in = st[d - 1];
@@ -309,15 +379,14 @@ hipError_t forward(const FftConv& f, const float* src, const int64_t* st, const 
   float2* other = (cur == out) ? tmp : out;
   hipError_t err;
   const RowIO none{};
-  if ((err = rows_t<false, true, false>(cur, T / f.ax[d - 1].n, f.ax[d - 1], f.tw[d - 1], io, s)) != hipSuccess)
+  if ((err = rows_t<false, true, false, true>(cur, T / ext[d - 1], f.ax[d - 1], f.tw[d - 1], io, s)) != hipSuccess)
     return err;
   for (int a = d - 1; a >= 1; --a) {
-    if ((err = transpose(cur, T / f.ax[a].n, f.ax[a].n, other, s)) != hipSuccess) return err;
+    if ((err = transpose(cur, T / ext[a], ext[a], other, s)) != hipSuccess) return err;
     float2* t = cur;
     cur = other;
     other = t;
-    if ((err = rows_t<false, false, false>(cur, T / f.ax[a - 1].n, f.ax[a - 1], f.tw[a - 1], none, s)) !=
-        hipSuccess)
+    if ((err = rows_t<false, false, false>(cur, T / ext[a - 1], f.ax[a - 1], f.tw[a - 1], none, s)) != hipSuccess)
       return err;
   }
   return hipSuccess;
@@ -328,11 +397,13 @@ hipError_t forward(const FftConv& f, const float* src, const int64_t* st, const 
 hipError_t launch_conv_fft(const FftConv& f, hipStream_t s) {
   const int d = f.rank;
   hipError_t err;
-  for (int a = 0; a < d; ++a)
-    hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((f.ax[a].n + 255) / 256)), dim3(256), 0, s, f.tw[a], f.ax[a].n);
+  for (int a = 0; a < d; ++a) {
+    const int n = a == d - 1 ? 2 * f.ax[a].n : f.ax[a].n;  // the last axis: the full real length
+    hipLaunchKernelGGL(fft_twiddles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f.tw[a], n);
+  }
   if ((err = hipGetLastError()) != hipSuccess) return err;
-  int64_t T = 1;
-  for (int a = 0; a < d; ++a) T *= f.ax[a].n;
+  int64_t ext[3], T;
+  stored_extents(f, ext, T);
   const int64_t kst[3] = {d == 3 ? (int64_t)f.kn[1] * f.kn[2] : (int64_t)f.kn[1], d == 3 ? (int64_t)f.kn[2] : 1, 1};
   if ((err = forward(f, f.x, f.xs, f.xn, f.A, f.B, s)) != hipSuccess) return err;
   if ((err = forward(f, f.k, kst, f.kn, f.A, f.C, s)) != hipSuccess) return err;
@@ -341,30 +412,34 @@ hipError_t launch_conv_fft(const FftConv& f, hipStream_t s) {
   if ((err = hipGetLastError()) != hipSuccess) return err;
   // inverse, from the order (n_1, .., n_{d-1}, n_0): rows along n_0, then for
   // each further axis a transpose [first][rest] -> [rest][first] and rows along
-  // the axis now last; d - 1 transposes, the last rows pass writes y
+  // the axis now last; d - 1 transposes, the last rows pass (the real inverse
+  // of the halved axis) writes y
   float2* cur = f.B;
   float2* other = f.A;
   const RowIO none{};
-  if ((err = rows_t<true, false, false>(cur, T / f.ax[0].n, f.ax[0], f.tw[0], none, s)) != hipSuccess) return err;
+  if ((err = rows_t<true, false, false>(cur, T / ext[0], f.ax[0], f.tw[0], none, s)) != hipSuccess) return err;
   for (int a = 1; a < d; ++a) {
-    // the current first axis is n_a
-    if ((err = transpose(cur, f.ax[a].n, T / f.ax[a].n, other, s)) != hipSuccess) return err;
+    // the current first axis is axis a
+    if ((err = transpose(cur, ext[a], T / ext[a], other, s)) != hipSuccess) return err;
     float2* t = cur;
     cur = other;
     other = t;
     if (a < d - 1) {
-      if ((err = rows_t<true, false, false>(cur, T / f.ax[a].n, f.ax[a], f.tw[a], none, s)) != hipSuccess) return err;
+      if ((err = rows_t<true, false, false>(cur, T / ext[a], f.ax[a], f.tw[a], none, s)) != hipSuccess) return err;
     }
   }
   int64_t n_out = 1;
   for (int a = 0; a < d; ++a) n_out *= f.yn[a];
   if (n_out == 0) return hipSuccess;
+  // unnormalised inverses: n_a along every full axis, n / 2 along the halved one
+  double norm = f.ax[d - 1].n;
+  for (int a = 0; a < d - 1; ++a) norm *= f.ax[a].n;
   RowIO io{};
   io.y = f.y;
   io.yc = f.ys[d - 1];
   io.oc = f.o[d - 1];
   io.ow = f.yn[d - 1];
-  io.scale = (float)(1.0 / (double)T);
+  io.scale = (float)(1.0 / norm);
   if (d == 2) {
     io.nb = 1;
     io.OA = f.yn[0];
@@ -382,7 +457,7 @@ hipError_t launch_conv_fft(const FftConv& f, hipStream_t s) {
     io.ya = f.ys[0];
     io.yb = f.ys[1];
   }
-  return rows_t<true, false, true>(cur, (int64_t)io.OA * io.OB, f.ax[d - 1], f.tw[d - 1], io, s);
+  return rows_t<true, false, true, true>(cur, (int64_t)io.OA * io.OB, f.ax[d - 1], f.tw[d - 1], io, s);
 }
 
 }  // namespace ttc

@@ -55,10 +55,13 @@ hipError_t launch_conv_separable(const SepConv& c, hipStream_t s);
 
 // FFT branch of 2-D and 3-D FP32 convolution: x (strided) and k (contiguous)
 // zero-padded to a volume n_0 x .. x n_{d-1} (d = rank, leading axis first)
-// whose extents are products of the stage radices (2, 3, 4, 5), at most
-// kFftMaxN each; per-axis twiddle tables tw[a] (n_a entries); A, B and C are
-// complex volumes of n_0 .. n_{d-1} points (scratch, the spectrum of x, the
-// spectrum of k); the output y (strided) is full index n + o.
+// whose extents are at most kFftMaxN.  ax[a] is the transform plan of axis a
+// (n = product of the stage radices 2, 3, 4, 5), except that the last axis is
+// real: its padded extent is 2 ax[d-1].n, transformed as ax[d-1].n complex
+// points and stored as ax[d-1].n + 1 frequencies.  Per-axis twiddle tables
+// tw[a] (n_a entries; 2 ax[d-1].n for the last axis); A, B and C are complex
+// volumes of the stored spectrum (scratch, the spectrum of x, the spectrum of
+// k); the output y (strided) is full index n + o.
 constexpr int kFftMaxN = 4096;
 constexpr int kFftMaxStages = 12;
 struct FftAxis {

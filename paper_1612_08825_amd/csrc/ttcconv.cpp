@@ -315,7 +315,7 @@ namespace {
 struct FftLayout {
   int rank = 0;
   FftAxis ax[3] = {};
-  int64_t volume = 0;  // n_0 .. n_{d-1}
+  int64_t volume = 0;  // stored spectrum points: n_0 .. n_{d-2} (n_{d-1} / 2 + 1)
   size_t tw[3] = {0, 0, 0}, A = 0, B = 0, C = 0, total = 0;
   int64_t oshape[TC_MAX_DIMS], off[TC_MAX_DIMS];
 };
@@ -344,6 +344,10 @@ FftAxis fft_axis(int64_t n) {
   }
 }
 
+// Every axis but the last is padded to the smallest 2^a 3^b 5^c holding the
+// full output; the last (real) axis to twice the smallest such number holding
+// half of it, transformed as half as many complex points and stored as its
+// n / 2 + 1 non-negative frequencies.
 int fft_layout(const tc_tensor* x, const tc_tensor* k, int32_t mode, FftLayout& L) {
   if (x->dtype != TC_F32 || k->dtype != TC_F32) return TC_EDTYPE;
   if (x->ndim != k->ndim || (x->ndim != 2 && x->ndim != 3)) return TC_ESHAPE;
@@ -351,20 +355,25 @@ int fft_layout(const tc_tensor* x, const tc_tensor* k, int32_t mode, FftLayout& 
   if ((st = conv_geometry(x, k, mode, L.oshape, L.off)) != TC_OK) return st;
   L.rank = (int)x->ndim;
   L.volume = 1;
-  int64_t n_min = kFftMaxN;
+  int64_t ext_min = INT64_MAX;
+  size_t tw_n[3];
   for (int a = 0; a < L.rank; ++a) {
     const int64_t full = x->shape[a] + k->shape[a] - 1;
-    if (full > kFftMaxN) return TC_ESHAPE;
-    L.ax[a] = fft_axis(full);
-    L.volume *= L.ax[a].n;
-    n_min = std::min<int64_t>(n_min, L.ax[a].n);
+    const bool last = a == L.rank - 1;
+    L.ax[a] = fft_axis(last ? (full + 1) / 2 : full);
+    const int64_t padded = last ? 2 * (int64_t)L.ax[a].n : L.ax[a].n;
+    if (padded > kFftMaxN) return TC_ESHAPE;
+    const int64_t ext = last ? L.ax[a].n + 1 : L.ax[a].n;
+    L.volume *= ext;
+    ext_min = std::min(ext_min, ext);
+    tw_n[a] = (size_t)padded;
   }
-  // one work-group per row: at most 2^31 - 1 rows along any axis
-  if (L.volume / n_min > INT32_MAX) return TC_ESHAPE;
+  // one work-group per row at most: at most 2^31 - 1 rows along any axis
+  if (L.volume / ext_min > INT32_MAX) return TC_ESHAPE;
   size_t o = 0;
   for (int a = 0; a < L.rank; ++a) {
     L.tw[a] = o;
-    o += fft_align((size_t)L.ax[a].n * sizeof(float2));
+    o += fft_align(tw_n[a] * sizeof(float2));
   }
   const size_t vol = fft_align((size_t)L.volume * sizeof(float2));
   L.A = o;
@@ -454,7 +463,7 @@ namespace {
 // The kernel side from which the FFT branch beats the direct kernels on
 // MI355X (FP32, full mode, cubic kernels): 2048 x 2048 images, and 3-D
 // volumes of 64 x 256 x 256.
-constexpr int kFftThreshold2D = 27;
+constexpr int kFftThreshold2D = 19;
 constexpr int kFftThreshold3D = 9;
 // Relative tolerance of the rank-one test the dispatcher applies to a host copy
 // of a square FP32 kernel (max |k - u v^T| <= tol * max |k|).

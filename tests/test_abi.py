@@ -279,17 +279,20 @@ def _fft_axis_extent(n):
 
 def test_fft_workspace_follows_the_padding_rule(lib):
     """tc_conv_fft_workspace_size: one twiddle table per axis and three complex
-    volumes, every axis padded to the smallest 2^a 3^b 5^c holding the full
-    output (at most 4096), 256-byte aligned pieces."""
+    volumes of the stored spectrum, every axis but the last padded to the
+    smallest 2^a 3^b 5^c holding the full output, the last (real) one to twice
+    that of half of it and stored as half plus one frequencies (at most 4096
+    points per axis), 256-byte aligned pieces."""
     al = lambda v: (v + 255) // 256 * 256
     cases = [((2048, 2048), (37, 37)), ((37, 50), (5, 7)), ((64, 256, 256), (15, 15, 15)), ((1, 1), (1, 1)),
              ((9, 20, 17), (3, 5, 4)), ((4000, 7), (97, 1))]
     for xs, ks in cases:
-        n = [_fft_axis_extent(a + b - 1) for a, b in zip(xs, ks)]
-        vol = 1
+        n = [_fft_axis_extent(a + b - 1) for a, b in zip(xs[:-1], ks[:-1])]
+        m = _fft_axis_extent((xs[-1] + ks[-1]) // 2)  # the real last axis: half its full extent, rounded up
+        vol = m + 1  # its stored frequencies
         for v in n:
             vol *= v
-        want = sum(al(v * 8) for v in n) + 3 * al(vol * 8)
+        want = sum(al(v * 8) for v in n) + al(2 * m * 8) + 3 * al(vol * 8)
         got = C.c_size_t(0)
         x, k = _desc(xs, L.TC_F32), _desc(ks, L.TC_F32)
         assert lib.tc_conv_fft_workspace_size(C.byref(x), C.byref(k), L.TC_FULL, C.byref(got)) == L.TC_OK

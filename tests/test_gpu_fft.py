@@ -23,9 +23,12 @@ let through a transform with a wrong twiddle in a late stage; the tests also
 hold the measured error to RATIO_MAX of the bound and to REL2_MAX relative to
 ||y64||_2 (rounding errors of an FFT grow like sqrt(log2 N) u on random data).
 
-Padded extents: each axis is padded to the smallest 2^a 3^b 5^c holding the
-full output; its stages are radix 4 while two factors of 2 remain, one radix 2
-for an odd one, then the 3s and the 5s (`fft_axis` below restates that rule).
+Padded extents: each axis but the last is padded to the smallest 2^a 3^b 5^c
+holding the full output; its stages are radix 4 while two factors of 2 remain,
+one radix 2 for an odd one, then the 3s and the 5s (`fft_axis` below restates
+that rule).  The last axis is real: it is padded to twice such a number
+holding half the full output and transformed as half as many complex points
+(`axis_plan`).
 """
 import math
 
@@ -57,8 +60,23 @@ def fft_axis(n):
         m += 1
 
 
+def axis_plan(xs, ks):
+    """(padded extent, stages) per axis: the last (real) axis is transformed as
+    half as many complex points, padded to twice a 2^a 3^b 5^c, plus the real
+    post-/pre-step, charged as one more radix-2 stage."""
+    out = []
+    for i, (a, b) in enumerate(zip(xs, ks)):
+        full = a + b - 1
+        if i == len(xs) - 1:
+            m, st = fft_axis((full + 1) // 2)
+            out.append((2 * m, st + [2]))
+        else:
+            out.append(fft_axis(full))
+    return out
+
+
 def tau_fft(xs, ks):
-    stages = sum((fft_axis(a + b - 1)[1] for a, b in zip(xs, ks)), [])
+    stages = sum((st for _, st in axis_plan(xs, ks)), [])
     return 3 * U * sum(8 * math.log2(R) + 2 * (R - 1) for R in stages) + 4 * U
 
 
@@ -76,7 +94,7 @@ def check(x, k, y, ref):
     assert e2 <= bound, (e2, bound)
     # the worst case sits far above typical errors only once there are a few
     # stages (a 1 x 1 transform is one rounded product, at the bound's scale)
-    n_stages = sum(len(fft_axis(a + b - 1)[1]) for a, b in zip(x.shape, k.shape))
+    n_stages = sum(len(st) for _, st in axis_plan(x.shape, k.shape))
     if n_stages >= 4:
         assert e2 <= RATIO_MAX * bound, (e2, bound)
     n2 = float(np.linalg.norm(ref))
@@ -180,7 +198,7 @@ def test_rejections(api):
 @pytest.mark.parametrize("xs,ks", [((41, 52), (5, 9)), ((27, 22), (19, 3)), ((60, 7), (16, 24)), ((125, 2), (1, 1))])
 def test_fft_mixed_radix_2d(api, xs, ks):
     """Padded extents with factors 3 and 5 (every radix the row pass has)."""
-    radices = {R for a, b in zip(xs, ks) for R in fft_axis(a + b - 1)[1]}
+    radices = {R for _, st in axis_plan(xs, ks) for R in st}
     assert radices & {3, 5}
     rng = np.random.default_rng(11 + sum(xs))
     x = rng.normal(0, 1, xs).astype(np.float32)
@@ -189,7 +207,7 @@ def test_fft_mixed_radix_2d(api, xs, ks):
         y = api.conv_fft(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode)
         ref = O.conv(x.astype(np.float64), k.astype(np.float64), mode)
         r = check(x, k, y.cpu().numpy(), ref)
-        print(f"[fft] {xs}*{ks} {mode} (padded {[fft_axis(a + b - 1)[0] for a, b in zip(xs, ks)]}): {r:.4f}")
+        print(f"[fft] {xs}*{ks} {mode} (padded {[n for n, _ in axis_plan(xs, ks)]}): {r:.4f}")
 
 
 SHAPES_3D = [((9, 20, 17), (3, 5, 4)), ((16, 16, 16), (9, 9, 9)), ((5, 31, 40), (5, 2, 7)), ((1, 1, 1), (1, 1, 1)),
