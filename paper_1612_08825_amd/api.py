@@ -189,7 +189,10 @@ SEPARABLE_SIZES = (3, 5, 7, 9, 11, 15)
 # Kernel side length from which the FFT branch beats the direct kernels on
 # MI355X (FP32, full mode, cubic kernels; bench.py's crossover sweeps): 2048 x
 # 2048 images, and 64 x 256 x 256 volumes.  The library's dispatcher
-# (tc_conv_nd_ex) uses the same values.
+# (tc_conv_nd_ex) uses the same values.  The FFT branch's error is norm-wise,
+# ||y - y64||_2 <= TAU ||x||_2 ||k||_1 with TAU = 3 u sum over the transform's
+# radix-R stages of (8 log2 R + 2 (R - 1)) + 4 u (u = 2^-24; about 4.3e-5 for a
+# 2048^2 image), not the element-wise (|x| (*) |k|) bound of the direct path.
 FFT_THRESHOLD = 19
 FFT_THRESHOLD_3D = 9
 FFT_MAX_N = 4096
