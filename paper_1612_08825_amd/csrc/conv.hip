@@ -554,11 +554,15 @@ hipError_t launch_sep_rb(const RowArgs& ra, const SepTaps& tp, hipStream_t s) {
   }
 }
 
+// Bands of 16 output rows when that still gives about two waves per SIMD
+// (2048 items), else 8 (timed on 1024^2 .. 4096^2 images with 7 and 15 taps:
+// 16 rows beat 32 by 16% at 4096^2, 8 rows win below; 64 rows lose
+// everywhere).  The band height never changes a result.
 template <int K>
 hipError_t launch_sep_k(const RowArgs& ra, const SepTaps& tp, hipStream_t s) {
   constexpr int LO = row_lanes_out<K, 3>();
-  const int64_t items32 = (int64_t)((ra.OH + 31) / 32) * ((ra.OW + 4 * LO - 1) / (4 * LO));
-  if (items32 >= 2048) return launch_sep_rb<K, 32>(ra, tp, s);
+  const int64_t items16 = (int64_t)((ra.OH + 15) / 16) * ((ra.OW + 4 * LO - 1) / (4 * LO));
+  if (items16 >= 2048) return launch_sep_rb<K, 16>(ra, tp, s);
   return launch_sep_rb<K, 8>(ra, tp, s);
 }
 
