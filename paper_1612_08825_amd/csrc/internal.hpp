@@ -114,9 +114,30 @@ struct VariantLevels {
   int64_t n[TC_MAX_LEVELS];         // positions summed per level
 };
 int variant_sum_blocks(int64_t positions);
-hipError_t launch_lowpass3(const float* src, int H, int W, float* dst, hipStream_t s);
-hipError_t launch_stencil_sums(int stencil, const Image2D& a, const Image2D& b, int Hl, int Wl, int level, int H0,
-                               int W0, double* part, int blocks, hipStream_t s);
+// The two frames of a pair: sources (any input type, strided) and FP32
+// destinations (contiguous rows); [0] the previous frame, [1] the next.
+struct VariantPlanes2 {
+  const void* p[2];
+  int64_t s0[2], s1[2];
+};
+struct VariantPair2 {
+  const float* src[2];
+  float* dst[2];
+};
+// Per level: the two frames' planes (level 0: the frames, input type; above:
+// FP32 level images), extents, work-groups and first partial.
+struct VariantSumLevels {
+  const void* a[TC_MAX_LEVELS];
+  const void* b[TC_MAX_LEVELS];
+  int64_t s0[2][TC_MAX_LEVELS], s1[2][TC_MAX_LEVELS];
+  int Hl[TC_MAX_LEVELS], Wl[TC_MAX_LEVELS], blocks[TC_MAX_LEVELS];
+  int64_t part_off[TC_MAX_LEVELS];
+};
+hipError_t launch_pyramid_pair(const VariantPlanes2& src, int dt, const VariantPair2& io, int Ho, int Wo,
+                               hipStream_t s);
+hipError_t launch_lowpass3_pair(const VariantPair2& io, int H, int W, hipStream_t s);
+hipError_t launch_stencil_sums_levels(int stencil, int dt, const VariantSumLevels& ls, int levels, int H0, int W0,
+                                      double* part, hipStream_t s);
 hipError_t launch_variant_finish(const double* part, const VariantLevels& lv, tc_ttc_level* out, tc_ttc_pick* pick,
                                  hipStream_t s);
 

@@ -3,10 +3,13 @@
 // path used to compare the paper's variants; the fused pass serves the
 // 2x2x2 cube without a low-pass filter).
 //
+// pyramid_pair:  the 2x2 block mean of both frames of the pair, one launch.
 // lowpass3:      P <- [1, 2, 1]/4 along rows and columns, borders clamped
 //                (Time to Contact, Results: a low-pass filter after the block
-//                mean; the filter itself is a reading, binomial).
-// stencil_sums:  one level's ten sums of the normal equations.  Per position
+//                mean; the filter itself is a reading, binomial); both frames
+//                in one launch.
+// stencil_sums:  one level's ten sums of the normal equations (all levels in
+//                one launch, stencil_sums_levels).  Per position
 //                the derivatives are formed in FP32 from the two frames, then
 //                G, the products and every sum are FP64; each block writes its
 //                partial sums (fixed order, deterministic).
@@ -32,8 +35,10 @@ namespace {
 
 constexpr int kSumThreads = 256;
 
-__global__ __launch_bounds__(256) void lowpass3(const float* __restrict__ src, int H, int W,
-                                                 float* __restrict__ dst) {
+// blockIdx.z: the frame (src[z] -> dst[z]).
+__global__ __launch_bounds__(256) void lowpass3(VariantPair2 io, int H, int W) {
+  const float* __restrict__ src = io.src[blockIdx.z];
+  float* __restrict__ dst = io.dst[blockIdx.z];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= W) return;
   const int jm = j > 0 ? j - 1 : 0, jp = j + 1 < W ? j + 1 : W - 1;
@@ -48,6 +53,25 @@ __global__ __launch_bounds__(256) void lowpass3(const float* __restrict__ src, i
       acc += wr[a + 1] * h;
     }
     dst[(int64_t)i * W + j] = acc;
+  }
+}
+
+// The 2x2 block mean of both frames of the pair in one launch (blockIdx.z:
+// the frame): P_{l+1}[i][j] = ((P[2i][2j] + P[2i][2j+1]) + (P[2i+1][2j] +
+// P[2i+1][2j+1])) / 4, the same order as the pyramid kernel.
+template <typename T>
+__global__ __launch_bounds__(256) void pyramid_pair(VariantPlanes2 src, VariantPair2 io, int Ho, int Wo) {
+  const T* __restrict__ sp = static_cast<const T*>(src.p[blockIdx.z]);
+  const int64_t s0 = src.s0[blockIdx.z], s1 = src.s1[blockIdx.z];
+  float* __restrict__ dst = io.dst[blockIdx.z];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Wo) return;
+  for (int i = blockIdx.y; i < Ho; i += gridDim.y) {
+    const T* r0 = sp + (int64_t)(2 * i) * s0 + (int64_t)(2 * j) * s1;
+    const T* r1 = r0 + s0;
+    const float a = to_f32<T>(r0[0]), b = to_f32<T>(r0[s1]);
+    const float c = to_f32<T>(r1[0]), d = to_f32<T>(r1[s1]);
+    dst[(int64_t)i * Wo + j] = ((a + b) + (c + d)) * 0.25f;
   }
 }
 
@@ -68,9 +92,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// The sums of work-group blockIdx.x of `nblocks` (positions strided by nblocks
+// work-groups).
 template <typename T, int ST>
-__global__ __launch_bounds__(kSumThreads) void stencil_sums(Plane a, Plane b, int Hl, int Wl, int level, int H0,
-                                                             int W0, double* __restrict__ part) {
+__device__ __forceinline__ void stencil_sums(Plane a, Plane b, int Hl, int Wl, int level, int H0, int W0,
+                                             int nblocks, double* __restrict__ part) {
   constexpr int K = ST == 0 ? 2 : 3;
   constexpr int B0 = ST == 0 ? 0 : 1;  // first position row / column
   const int nr = Hl - K + 1, nc = Wl - K + 1;
@@ -80,7 +106,7 @@ __global__ __launch_bounds__(kSumThreads) void stencil_sums(Plane a, Plane b, in
   double acc[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-  for (int64_t p = (int64_t)blockIdx.x * kSumThreads + threadIdx.x; p < n; p += (int64_t)gridDim.x * kSumThreads) {
+  for (int64_t p = (int64_t)blockIdx.x * kSumThreads + threadIdx.x; p < n; p += (int64_t)nblocks * kSumThreads) {
     const int i = B0 + (int)(p / nc), j = B0 + (int)(p % nc);
     float fx, fy, ft;
     if constexpr (ST == 0) {
@@ -140,6 +166,22 @@ __global__ __launch_bounds__(kSumThreads) void stencil_sums(Plane a, Plane b, in
   }
 }
 
+// Every level's sums in one launch: blockIdx.y is the level (its planes are
+// the frames themselves at level 0, FP32 level images above), and a level
+// runs on its own first `blocks` work-groups, as separate launches would.
+template <typename T, int ST>
+__global__ __launch_bounds__(kSumThreads) void stencil_sums_levels(VariantSumLevels ls, int H0, int W0,
+                                                                    double* __restrict__ part) {
+  const int l = blockIdx.y;
+  if ((int)blockIdx.x >= ls.blocks[l]) return;  // uniform
+  const Plane a{ls.a[l], ls.s0[0][l], ls.s1[0][l]}, b{ls.b[l], ls.s0[1][l], ls.s1[1][l]};
+  double* pl = part + ls.part_off[l] * 10;
+  if (l == 0)
+    stencil_sums<T, ST>(a, b, ls.Hl[l], ls.Wl[l], l, H0, W0, ls.blocks[l], pl);
+  else
+    stencil_sums<float, ST>(a, b, ls.Hl[l], ls.Wl[l], l, H0, W0, ls.blocks[l], pl);
+}
+
 __global__ __launch_bounds__(64 * TC_MAX_LEVELS) void variant_finish(const double* __restrict__ part, VariantLevels lv,
                                                                      tc_ttc_level* __restrict__ out,
                                                                      tc_ttc_pick* __restrict__ pick) {
@@ -183,22 +225,29 @@ __global__ __launch_bounds__(64 * TC_MAX_LEVELS) void variant_finish(const doubl
 }
 
 template <typename T>
-hipError_t sums_t(int stencil, const Image2D& a, const Image2D& b, int Hl, int Wl, int level, int H0, int W0,
-                  double* part, int blocks, hipStream_t s) {
-  const Plane pa{a.p, a.s0, a.s1}, pb{b.p, b.s0, b.s1};
-  const dim3 grid((unsigned)blocks), block(kSumThreads);
+hipError_t sums_t(int stencil, const VariantSumLevels& ls, int levels, int H0, int W0, double* part, hipStream_t s) {
+  int bmax = 1;
+  for (int l = 0; l < levels; ++l) bmax = ls.blocks[l] > bmax ? ls.blocks[l] : bmax;
+  const dim3 grid((unsigned)bmax, (unsigned)levels), block(kSumThreads);
   switch (stencil) {
     case TC_STENCIL_FD2:
-      hipLaunchKernelGGL((stencil_sums<T, 0>), grid, block, 0, s, pa, pb, Hl, Wl, level, H0, W0, part);
+      hipLaunchKernelGGL((stencil_sums_levels<T, 0>), grid, block, 0, s, ls, H0, W0, part);
       break;
     case TC_STENCIL_PREWITT3:
-      hipLaunchKernelGGL((stencil_sums<T, 2>), grid, block, 0, s, pa, pb, Hl, Wl, level, H0, W0, part);
+      hipLaunchKernelGGL((stencil_sums_levels<T, 2>), grid, block, 0, s, ls, H0, W0, part);
       break;
     case TC_STENCIL_SOBEL3:
-      hipLaunchKernelGGL((stencil_sums<T, 3>), grid, block, 0, s, pa, pb, Hl, Wl, level, H0, W0, part);
+      hipLaunchKernelGGL((stencil_sums_levels<T, 3>), grid, block, 0, s, ls, H0, W0, part);
       break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pyr_pair_t(const VariantPlanes2& src, const VariantPair2& io, int Ho, int Wo, hipStream_t s) {
+  const unsigned gy = (unsigned)(Ho < 65535 ? Ho : 65535);
+  hipLaunchKernelGGL(pyramid_pair<T>, dim3((unsigned)((Wo + 255) / 256), gy, 2), dim3(256), 0, s, src, io, Ho, Wo);
   return hipGetLastError();
 }
 
@@ -209,19 +258,30 @@ int variant_sum_blocks(int64_t positions) {
   return (int)(b < 1 ? 1 : b > 2048 ? 2048 : b);
 }
 
-hipError_t launch_lowpass3(const float* src, int H, int W, float* dst, hipStream_t s) {
+hipError_t launch_pyramid_pair(const VariantPlanes2& src, int dt, const VariantPair2& io, int Ho, int Wo,
+                               hipStream_t s) {
+  if (Ho <= 0 || Wo <= 0) return hipSuccess;
+  switch (dt) {
+    case TC_U8: return pyr_pair_t<uint8_t>(src, io, Ho, Wo, s);
+    case TC_F16: return pyr_pair_t<_Float16>(src, io, Ho, Wo, s);
+    case TC_F32: return pyr_pair_t<float>(src, io, Ho, Wo, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_lowpass3_pair(const VariantPair2& io, int H, int W, hipStream_t s) {
   if (H <= 0 || W <= 0) return hipSuccess;
   const unsigned gy = (unsigned)(H < 65535 ? H : 65535);
-  hipLaunchKernelGGL(lowpass3, dim3((unsigned)((W + 255) / 256), gy), dim3(256), 0, s, src, H, W, dst);
+  hipLaunchKernelGGL(lowpass3, dim3((unsigned)((W + 255) / 256), gy, 2), dim3(256), 0, s, io, H, W);
   return hipGetLastError();
 }
 
-hipError_t launch_stencil_sums(int stencil, const Image2D& a, const Image2D& b, int Hl, int Wl, int level, int H0,
-                               int W0, double* part, int blocks, hipStream_t s) {
-  switch (a.dt) {
-    case TC_U8: return sums_t<uint8_t>(stencil, a, b, Hl, Wl, level, H0, W0, part, blocks, s);
-    case TC_F16: return sums_t<_Float16>(stencil, a, b, Hl, Wl, level, H0, W0, part, blocks, s);
-    case TC_F32: return sums_t<float>(stencil, a, b, Hl, Wl, level, H0, W0, part, blocks, s);
+hipError_t launch_stencil_sums_levels(int stencil, int dt, const VariantSumLevels& ls, int levels, int H0, int W0,
+                                      double* part, hipStream_t s) {
+  switch (dt) {
+    case TC_U8: return sums_t<uint8_t>(stencil, ls, levels, H0, W0, part, s);
+    case TC_F16: return sums_t<_Float16>(stencil, ls, levels, H0, W0, part, s);
+    case TC_F32: return sums_t<float>(stencil, ls, levels, H0, W0, part, s);
     default: return hipErrorInvalidValue;
   }
 }

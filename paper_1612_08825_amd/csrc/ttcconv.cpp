@@ -981,7 +981,7 @@ namespace {
 struct VariantLayout {
   int64_t Hl[TC_MAX_LEVELS], Wl[TC_MAX_LEVELS];
   size_t level_off[2][TC_MAX_LEVELS];
-  size_t tmp_off = 0, part_off = 0, total = 0;
+  size_t tmp_off[2] = {0, 0}, part_off = 0, total = 0;
   VariantLevels lv{};
 };
 
@@ -1009,8 +1009,11 @@ int variant_layout(int64_t H, int64_t W, int32_t levels, int32_t stencil, int32_
       L.level_off[f][l] = off;
       off += align_up((size_t)(L.Hl[l] * L.Wl[l]) * sizeof(float));
     }
-  L.tmp_off = off;
-  if (lowpass == TC_LOWPASS_BINOMIAL3 && levels > 1) off += align_up((size_t)(L.Hl[1] * L.Wl[1]) * sizeof(float));
+  // the block means before the low-pass, both frames
+  for (int f = 0; f < 2; ++f) {
+    L.tmp_off[f] = off;
+    if (lowpass == TC_LOWPASS_BINOMIAL3 && levels > 1) off += align_up((size_t)(L.Hl[1] * L.Wl[1]) * sizeof(float));
+  }
   L.part_off = off;
   off += align_up((size_t)parts * 10 * sizeof(double));
   L.total = off;
@@ -1047,26 +1050,45 @@ extern "C" int tc_ttc_solve_variant(const tc_tensor* prev, const tc_tensor* next
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   char* w = static_cast<char*>(ws);
   double* part = reinterpret_cast<double*>(w + L.part_off);
-  Image2D cur[2] = {Image2D{prev->data, prev->dtype, prev->stride[0], prev->stride[1]},
-                    Image2D{next->data, next->dtype, next->stride[0], next->stride[1]}};
+  // both frames' levels (one launch per level and step), then every level's
+  // sums in one launch
+  VariantSumLevels ls{};
+  VariantPlanes2 cur{{prev->data, next->data}, {prev->stride[0], next->stride[0]}, {prev->stride[1], next->stride[1]}};
+  int cur_dt = prev->dtype;
   for (int l = 0; l < levels; ++l) {
     const int Hl = (int)L.Hl[l], Wl = (int)L.Wl[l];
-    if (l > 0)
-      for (int f = 0; f < 2; ++f) {
-        float* dst = reinterpret_cast<float*>(w + L.level_off[f][l]);
-        if (lowpass == TC_LOWPASS_BINOMIAL3) {
-          float* tmp = reinterpret_cast<float*>(w + L.tmp_off);
-          if (launch_pyramid_level(cur[f], tmp, Wl, 1, Hl, Wl, s) != hipSuccess) return TC_EDEVICE;
-          if (launch_lowpass3(tmp, Hl, Wl, dst, s) != hipSuccess) return TC_EDEVICE;
-        } else if (launch_pyramid_level(cur[f], dst, Wl, 1, Hl, Wl, s) != hipSuccess) {
-          return TC_EDEVICE;
-        }
-        cur[f] = Image2D{dst, TC_F32, Wl, 1};
+    if (l > 0) {
+      VariantPair2 io{};
+      for (int f = 0; f < 2; ++f) io.dst[f] = reinterpret_cast<float*>(w + L.level_off[f][l]);
+      if (lowpass == TC_LOWPASS_BINOMIAL3) {
+        VariantPair2 blk{};
+        for (int f = 0; f < 2; ++f) blk.dst[f] = reinterpret_cast<float*>(w + L.tmp_off[f]);
+        if (launch_pyramid_pair(cur, cur_dt, blk, Hl, Wl, s) != hipSuccess) return TC_EDEVICE;
+        for (int f = 0; f < 2; ++f) io.src[f] = blk.dst[f];
+        if (launch_lowpass3_pair(io, Hl, Wl, s) != hipSuccess) return TC_EDEVICE;
+      } else if (launch_pyramid_pair(cur, cur_dt, io, Hl, Wl, s) != hipSuccess) {
+        return TC_EDEVICE;
       }
-    if (launch_stencil_sums(stencil, cur[0], cur[1], Hl, Wl, l, (int)H, (int)W, part + L.lv.part_off[l] * 10,
-                            L.lv.blocks[l], s) != hipSuccess)
-      return TC_EDEVICE;
+      for (int f = 0; f < 2; ++f) {
+        cur.p[f] = io.dst[f];
+        cur.s0[f] = Wl;
+        cur.s1[f] = 1;
+      }
+      cur_dt = TC_F32;
+    }
+    ls.a[l] = cur.p[0];
+    ls.b[l] = cur.p[1];
+    for (int f = 0; f < 2; ++f) {
+      ls.s0[f][l] = cur.s0[f];
+      ls.s1[f][l] = cur.s1[f];
+    }
+    ls.Hl[l] = Hl;
+    ls.Wl[l] = Wl;
+    ls.blocks[l] = L.lv.blocks[l];
+    ls.part_off[l] = L.lv.part_off[l];
   }
+  if (launch_stencil_sums_levels(stencil, prev->dtype, ls, levels, (int)H, (int)W, part, s) != hipSuccess)
+    return TC_EDEVICE;
   return hip_status(launch_variant_finish(part, L.lv, levels_out, pick_out, s));
 }
 
