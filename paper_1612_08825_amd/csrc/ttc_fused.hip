@@ -86,11 +86,18 @@ __device__ __forceinline__ void sum_diff(const Raw8<_Float16>& a, const Raw8<_Fl
   }
 }
 
+// Which cube columns of a lane may need masking.  kEdgeNone: every lane owns
+// all or none of its columns at every level.  kEdgeLast: a lane with a partial
+// set lacks only its last column at each level (always so when W is a multiple
+// of 8: its last base column W - 1 has no right neighbour).  kEdgeAny: any other
+// partial set.
+enum EdgeMode { kEdgeNone = 0, kEdgeLast = 1, kEdgeAny = 2 };
+
 // Accumulate the cubes of one row of one level.  hd*, hs*, hD* are the horizontal
-// quantities of the previous (p) and current level rows.  EDGE: some lane of the
-// wave has a partial set of valid columns at this level; cubes at columns
-// c >= ncv then contribute zero (their derivatives are masked).
-template <int NC, bool EDGE>
+// quantities of the previous (p) and current level rows.  Cubes at columns
+// c >= ncv contribute zero (their derivatives are masked), checked at the
+// columns the edge mode EM names.
+template <int NC, int EM>
 __device__ __forceinline__ void cubes(float (&acc)[10], const float (&hdp)[NC], const float (&hd)[NC],
                                       const float (&hsp)[NC], const float (&hs)[NC], const float (&hDp)[NC],
                                       const float (&hD)[NC], int ncv, const float (&xc)[NC], float y) {
@@ -99,7 +106,7 @@ __device__ __forceinline__ void cubes(float (&acc)[10], const float (&hdp)[NC], 
     float ex = hdp[c] + hd[c];
     float ey = hs[c] - hsp[c];
     float et = hDp[c] + hD[c];
-    if constexpr (EDGE) {
+    if (EM == kEdgeAny || (EM == kEdgeLast && NC > 1 && c == NC - 1)) {
       const bool ok = c < ncv;
       ex = ok ? ex : 0.f;
       ey = ok ? ey : 0.f;
@@ -181,7 +188,7 @@ struct Walk {
 // One group of NJ (<= 8) rows.  a[j], b[j] hold row j of the pair's two frames;
 // refill(a[j], b[j], j) loads row j of the next group into them once row j's S
 // and D are formed.  CHECK: rows j >= rows_left do not exist (the bottom band).
-template <int KIND, int NJ, bool EDGE, bool CHECK, typename REFILL>
+template <int KIND, int NJ, int EM, bool CHECK, typename REFILL>
 __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T> (&b)[kGroup], REFILL&& refill,
                                            int rows_left, const int (&ncv)[LV], const float (&xc0)[8],
                                            const float (&xc1)[4], const float (&xc2)[2], const float (&xc3)[1],
@@ -199,7 +206,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
       float hs0[8], hd0[8], hD0[8];
       horizontals<8>(S, D, hs0, hd0, hD0);
       if constexpr (owns<KIND>(j, 0))
-        cubes<8, EDGE>(s.acc[0], s.hd0p, hd0, s.hs0p, hs0, s.hD0p, hD0, ncv[0], xc0, s.y[0] + (float)j);
+        cubes<8, EM>(s.acc[0], s.hd0p, hd0, s.hs0p, hs0, s.hD0p, hD0, ncv[0], xc0, s.y[0] + (float)j);
       if constexpr (LV >= 2 && (j & 1) == 1) {
         float U1[4], V1[4];
 #pragma unroll
@@ -210,7 +217,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
         float hs1[4], hd1[4], hD1[4];
         horizontals<4>(U1, V1, hs1, hd1, hD1);
         if constexpr (owns<KIND>(j, 1))
-          cubes<4, EDGE>(s.acc[1], s.hd1p, hd1, s.hs1p, hs1, s.hD1p, hD1, ncv[1], xc1, s.y[1] + (float)(j >> 1));
+          cubes<4, EM>(s.acc[1], s.hd1p, hd1, s.hs1p, hs1, s.hD1p, hD1, ncv[1], xc1, s.y[1] + (float)(j >> 1));
         if constexpr (LV >= 3 && (j & 3) == 3) {
           float U2[2], V2[2];
 #pragma unroll
@@ -221,7 +228,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
           float hs2[2], hd2[2], hD2[2];
           horizontals<2>(U2, V2, hs2, hd2, hD2);
           if constexpr (owns<KIND>(j, 2))
-            cubes<2, EDGE>(s.acc[2], s.hd2p, hd2, s.hs2p, hs2, s.hD2p, hD2, ncv[2], xc2, s.y[2] + (float)(j >> 2));
+            cubes<2, EM>(s.acc[2], s.hd2p, hd2, s.hs2p, hs2, s.hD2p, hD2, ncv[2], xc2, s.y[2] + (float)(j >> 2));
           if constexpr (LV >= 4 && (j & 7) == 7) {
             float U3[1], V3[1];
             U3[0] = s.hs2p[0] + hs2[0];
@@ -229,7 +236,7 @@ __device__ __forceinline__ void walk_group(Walk& s, Raw8<T> (&a)[kGroup], Raw8<T
             float hs3[1], hd3[1], hD3[1];
             horizontals<1>(U3, V3, hs3, hd3, hD3);
             if constexpr (owns<KIND>(j, 3))
-              cubes<1, EDGE>(s.acc[3], s.hd3p, hd3, s.hs3p, hs3, s.hD3p, hD3, ncv[3], xc3, s.y[3]);
+              cubes<1, EM>(s.acc[3], s.hd3p, hd3, s.hs3p, hs3, s.hD3p, hD3, ncv[3], xc3, s.y[3]);
             s.hs3p[0] = hs3[0];
             s.hd3p[0] = hd3[0];
             s.hD3p[0] = hD3[0];
@@ -277,12 +284,12 @@ __device__ __forceinline__ void flush(Walk& s, float* tot, int lane) {
 }
 
 // One wave, one pair, one band: rows row0 .. row0 + RB + kHalo - 1 (fewer at
-// the bottom of the frame).  EDGE: some lane owns a partial set of cube
-// columns; CHECK: the band reaches the bottom of the frame or the stream is
-// not vector-aligned (rows and lane chunks are then loaded with checks).
+// the bottom of the frame).  EM: the edge mode (which cube columns are masked);
+// CHECK: the band reaches the bottom of the frame or the stream is not
+// vector-aligned (rows and lane chunks are then loaded with checks).
 // Leaves the lane's sums in tot[(l * 10 + q) * 64 + lane] (zero for a level at
 // which the lane owns no cube).
-template <bool EDGE, bool CHECK>
+template <int EM, bool CHECK>
 __device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, int RB, int c_lane, int lane,
                                           float* tot, float one) {
   const int H = d.H, W = d.W;
@@ -364,15 +371,15 @@ __device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, 
   };
   auto none = [&](Raw8<T>&, Raw8<T>&, int) {};
 
-  walk_group<kFirst, kGroup, EDGE, CHECK>(s, a, b, refill, n_rows, ncv, xc0, xc1, xc2, xc3, one);
+  walk_group<kFirst, kGroup, EM, CHECK>(s, a, b, refill, n_rows, ncv, xc0, xc1, xc2, xc3, one);
   // groups 1 .. inner_end - 1 lie inside the band, group inner_end is the halo
   const int inner_end = RB / kGroup;
   for (int g = 1; g < inner_end; ++g) {
     gw += kGroup;
-    walk_group<kInner, kGroup, EDGE, CHECK>(s, a, b, refill, n_rows - g * kGroup, ncv, xc0, xc1, xc2, xc3, one);
+    walk_group<kInner, kGroup, EM, CHECK>(s, a, b, refill, n_rows - g * kGroup, ncv, xc0, xc1, xc2, xc3, one);
     if (g & 1) flush(s, tot, lane);
   }
-  walk_group<kHaloGroup, kHalo, EDGE, CHECK>(s, a, b, none, n_rows - inner_end * kGroup, ncv, xc0, xc1, xc2, xc3,
+  walk_group<kHaloGroup, kHalo, EM, CHECK>(s, a, b, none, n_rows - inner_end * kGroup, ncv, xc0, xc1, xc2, xc3,
                                              one);
   // lanes that own no cube of a level contribute zero
 #pragma unroll
@@ -392,7 +399,7 @@ __device__ __forceinline__ void band_pair(const SeqDesc& d, int pair, int row0, 
   }
 }
 
-__global__ __launch_bounds__(64) void ttc_fused(FusedArgs a, int RB) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void ttc_fused(FusedArgs a, int RB) {
   __shared__ float tot[NV * 64];  // each lane's running sums, [value][lane]
   __shared__ float red[8 * NV];
   const int lane = threadIdx.x;
@@ -420,20 +427,26 @@ __global__ __launch_bounds__(64) void ttc_fused(FusedArgs a, int RB) {
     // it (a lane chunk may run up to 7 pixels past column W)
     const int64_t below = (int64_t)d.H - row0 - (RB + kHalo);
     const bool check = !(d.vec && below >= 1);
-    // some lane owns a partial set of cube columns at some level
-    bool edge = false;
+    // some lane owns a partial set of cube columns at some level; `other`: one
+    // that lacks more than its last column there
+    bool edge = false, other = false;
 #pragma unroll
     for (int l = 0; l < LV; ++l) {
       const int n = (d.W >> l) - 1 - (c_lane >> l);
-      edge = edge || (lane < 63 && n > 0 && n < (8 >> l));
+      const bool part = lane < 63 && n > 0 && n < (8 >> l);
+      edge = edge || part;
+      other = other || (part && n != (8 >> l) - 1);
     }
-    edge = __any(edge);
-    if (edge) {
-      if (check) band_pair<true, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
-      else band_pair<true, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+    const int em = __any(other) ? kEdgeAny : (__any(edge) ? kEdgeLast : kEdgeNone);
+    if (em == kEdgeLast) {
+      if (check) band_pair<kEdgeLast, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+      else band_pair<kEdgeLast, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+    } else if (em == kEdgeAny) {
+      if (check) band_pair<kEdgeAny, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+      else band_pair<kEdgeAny, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
     } else {
-      if (check) band_pair<false, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
-      else band_pair<false, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+      if (check) band_pair<kEdgeNone, true>(d, pair, row0, RB, c_lane, lane, tot, a.one);
+      else band_pair<kEdgeNone, false>(d, pair, row0, RB, c_lane, lane, tot, a.one);
     }
 
     // One partial per (pair, level, band): the 10 LV values are summed over

@@ -60,6 +60,21 @@ def test_ragged_sizes(api, H, W, levels, dtype):
         check_pair(recs[t * levels:(t + 1) * levels], picks[t], v.frames[t], v.frames[t + 1], levels, f"{H}x{W}")
 
 
+@pytest.mark.parametrize("W", [64, 65, 71, 72, 505, 511, 512, 513, 519, 1008, 1009, 1016, 1023])
+@pytest.mark.parametrize("dtype", ["u8", "f16"])
+def test_edge_columns_every_residue(api, W, dtype):
+    """Widths around lane and column-wave boundaries, every residue mod 8: the
+    lane at the right edge lacks only its last cube column at each level when
+    W is a multiple of 8 (that column alone is masked) and other sets
+    otherwise (every column checked)."""
+    H = 40
+    v = synth.multiscale_video(H=H, W=W, F=3, foe=(W / 7, -H / 9), ttc_start=45, ttc_end=40, dtype=dtype)
+    fr = torch.from_numpy(v.frames).cuda()
+    recs, picks = api.ttc_solve_batched([fr], 4)
+    for t in range(2):
+        check_pair(recs[t * 4:(t + 1) * 4], picks[t], v.frames[t], v.frames[t + 1], 4, f"{H}x{W}")
+
+
 def test_batch_mix_equals_alone(api):
     """Streams of uneven sizes in one plan: each pair equals the oracle, and the
     records are bit-identical to running each stream alone."""
