@@ -146,12 +146,17 @@ hipError_t launch_horn(const Image2D& prev, const Image2D& next, int H, int W, v
 
 // ---------------------------------------------------------------- fused TTC
 // One entry of the device work table: a video stream and where its work and
-// results go.  The fused pass covers the stream with work items of one wave
-// each: one frame pair on a band of `band_rows` base rows by one column-wave of
-// 504 owned base columns (63 lanes x 8 columns; lane 63 only lends its columns
-// to lane 62).  A (column-wave, band) is a "witem"; items are numbered
-// witem-major (column-wave-major, band-minor) and pair-minor, so the items of
-// consecutive pairs of one band are adjacent, then vertically adjacent bands.
+// results go.  The fused pass covers each frame pair of the stream with
+// segments of `band_rows` base rows by `seg_cols` owned base columns; a
+// segment occupies seg_cols / 8 lanes that own 8 base columns each and one more
+// that only lends its first column to the lane before it.  A work item is one
+// wave and one pair: `seg_per_wave` consecutive segments side by side in its
+// lanes.  Segments are numbered first over the bands whose walk (owned rows and
+// 2^(levels-1) halo rows) has a row of the frame below it, column-strip-major
+// and band-minor, then over the remaining bottom bands, band-major, so that the
+// waves that reach the bottom of the frame hold segments of one height.  Items
+// are numbered wave-major, pair-minor, so that the items of consecutive pairs
+// over the same segments are adjacent.
 struct SeqDesc {
   const void* frame0;
   int64_t frame_stride;   // elements
@@ -159,18 +164,21 @@ struct SeqDesc {
   int32_t H, W;
   int32_t n_frames;
   int32_t levels;
-  int32_t band_rows;      // owned base rows per band (one wave)
+  int32_t band_rows;      // owned base rows per segment
   int32_t n_bands;        // ceil(H / band_rows)
-  int32_t n_cw;           // ceil((W - 1) / 504)
-  int32_t n_witems;       // bands x column-waves: partial sums per (pair, level)
+  int32_t seg_cols;       // owned base columns per segment (a multiple of 8, at most 504)
+  int32_t seg_lanes;      // lanes per segment: seg_cols / 8 + 1
+  int32_t seg_per_wave;   // segments per wave: floor(64 / seg_lanes)
+  int32_t n_waves;        // work items per pair: ceil(n_witems / seg_per_wave)
+  int32_t n_witems;       // segments (column strips x bands): partial sums per (pair, level)
+  int32_t n_strips;       // column strips: ceil((W - 1) / seg_cols)
+  int32_t n_full_bands;   // leading bands whose walk has a row of the frame below it
+  int32_t vec;            // 1: every 8-pixel lane chunk is aligned for one vector load
+  int32_t pad;
   int64_t item_begin;     // first work item of this stream (prefix over streams)
   int64_t pair_begin;     // first global pair index of this stream
   int64_t partial_begin;  // first float of this stream's partial sums
-  int32_t vec;            // 1: every 8-pixel lane chunk is aligned for one vector load
-  int32_t pad;
 };
-
-constexpr int kWaveCols = 504;  // owned base columns per wave (63 lanes x 8)
 
 struct FusedLaunch {
   int dt;           // TC_U8 or TC_F16

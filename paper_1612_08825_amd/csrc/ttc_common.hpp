@@ -41,13 +41,18 @@ __device__ __forceinline__ SeqDesc uniform(const SeqDesc& s) {
   d.levels = uni(s.levels);
   d.band_rows = uni(s.band_rows);
   d.n_bands = uni(s.n_bands);
-  d.n_cw = uni(s.n_cw);
+  d.seg_cols = uni(s.seg_cols);
+  d.seg_lanes = uni(s.seg_lanes);
+  d.seg_per_wave = uni(s.seg_per_wave);
+  d.n_waves = uni(s.n_waves);
+  d.n_witems = uni(s.n_witems);
+  d.n_strips = uni(s.n_strips);
+  d.n_full_bands = uni(s.n_full_bands);
+  d.vec = uni(s.vec);
+  d.pad = 0;
   d.item_begin = uni(s.item_begin);
   d.pair_begin = uni(s.pair_begin);
   d.partial_begin = uni(s.partial_begin);
-  d.n_witems = uni(s.n_witems);
-  d.vec = uni(s.vec);
-  d.pad = 0;
   return d;
 }
 

@@ -723,6 +723,40 @@ int vector_ok(const tc_seq& q, int dtype) {
          (q.frame_stride * es) % align == 0;
 }
 
+// Column strips of the fused pass: owned base columns per segment (a multiple
+// of 8, so that a lane's 8 columns are one level-3 column) with one lending lane
+// each, as many segments as fit in a wave.  Narrow strips let frames narrower
+// than a wave, and the last strip of a wider one, share a wave's lanes between
+// bands instead of leaving them idle.
+struct SegShape {
+  int cols, lanes, per_wave;
+};
+constexpr SegShape kSegShapes[] = {{504, 64, 1}, {248, 32, 2}, {160, 21, 3}, {120, 16, 4}};
+
+// The segment shape with the fewest waves per pair (every wave walks the same
+// rows); among equals the widest, which has the fewest lending lanes and partials.
+void choose_segments(SeqDesc& d) {
+  int64_t best = INT64_MAX;
+  for (const SegShape& g : kSegShapes) {
+    const int64_t strips = (d.W - 1 + g.cols - 1) / g.cols;  // W - 1 cube columns at level 0
+    const int64_t segs = strips * d.n_bands;
+    const int64_t waves = (segs + g.per_wave - 1) / g.per_wave;
+    if (waves < best) {
+      best = waves;
+      d.seg_cols = g.cols;
+      d.seg_lanes = g.lanes;
+      d.seg_per_wave = g.per_wave;
+      d.n_witems = (int32_t)segs;
+      d.n_waves = (int32_t)waves;
+      d.n_strips = (int32_t)strips;
+    }
+  }
+  // band b walks rows b RB .. b RB + RB + halo - 1 and needs row b RB + RB + halo
+  const int64_t walk = (int64_t)d.band_rows + (1 << (d.levels - 1));
+  const int64_t full = d.H - walk - 1 >= 0 ? (d.H - walk - 1) / d.band_rows + 1 : 0;
+  d.n_full_bands = (int32_t)std::min<int64_t>(full, d.n_bands);
+}
+
 void fill_desc(SeqDesc& d, const tc_seq& q, int dtype, int band_rows) {
   d.frame0 = q.frame0;
   d.frame_stride = q.frame_stride;
@@ -733,9 +767,7 @@ void fill_desc(SeqDesc& d, const tc_seq& q, int dtype, int band_rows) {
   d.levels = q.levels;
   d.band_rows = band_rows;
   d.n_bands = (q.H + band_rows - 1) / band_rows;
-  d.n_cw = (q.W - 1 + kWaveCols - 1) / kWaveCols;
-  d.n_witems = d.n_bands * d.n_cw;
-  d.pad = 0;
+  choose_segments(d);
   d.vec = vector_ok(q, dtype);
 }
 
@@ -762,7 +794,7 @@ static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
     d.item_begin = items;
     d.pair_begin = pairs;
     d.partial_begin = floats;
-    items += (int64_t)d.n_witems * (d.n_frames - 1);  // one work item per (band, pair)
+    items += (int64_t)d.n_waves * (d.n_frames - 1);  // one work item per (wave of segments, pair)
     pairs += d.n_frames - 1;
     floats += (int64_t)(d.n_frames - 1) * p->levels * d.n_witems * 10;
   }
@@ -787,7 +819,7 @@ static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
   int32_t* pair_seq = reinterpret_cast<int32_t*>(base + desc_bytes + item_bytes);
   for (int i = 0; i < n_seqs; ++i) {
     const SeqDesc& d = descs[(size_t)i];
-    for (int64_t k = 0; k < (int64_t)d.n_witems * (d.n_frames - 1); ++k) item_seq[d.item_begin + k] = i;
+    for (int64_t k = 0; k < (int64_t)d.n_waves * (d.n_frames - 1); ++k) item_seq[d.item_begin + k] = i;
     for (int64_t k = 0; k < d.n_frames - 1; ++k) pair_seq[d.pair_begin + k] = i;
   }
   p->n_seqs = n_seqs;
@@ -965,9 +997,12 @@ extern "C" int tc_ttc_workspace_size(int64_t H, int64_t W, int32_t levels, size_
     q.W = (int32_t)W;
     q.n_frames = 2;
     q.levels = levels;
-    SeqDesc d{};
-    fill_desc(d, q, dt, 16);  // the smallest band height has the most partials
-    best = std::max(best, pair_ws_bytes(d));
+    // every band height a tuning may use (segment shapes depend on it)
+    for (int rb = 16; rb <= 256; rb += 16) {
+      SeqDesc d{};
+      fill_desc(d, q, dt, rb);
+      best = std::max(best, pair_ws_bytes(d));
+    }
   }
   *ws_bytes = best;
   return TC_OK;
@@ -1106,7 +1141,7 @@ extern "C" int tc_ttc_solve(const tc_tensor* prev, const tc_tensor* next, int32_
   f.table = nullptr;
   f.n_seqs = 1;
   f.inl = d;
-  f.n_items = d.n_witems;
+  f.n_items = d.n_waves;
   f.n_pairs = 1;
   f.partials = reinterpret_cast<float*>(ws);
   f.grid = persistent_grid(f.n_items, kPairTuning.groups_per_cu);
