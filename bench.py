@@ -62,7 +62,7 @@ def parse():
 # ----------------------------------------------------------------------------- measured traffic
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "ttc_fused_batched64_f16_L4.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1612_08825_amd", "csrc", f)
-                  for f in ("ttc_fused.hip", "ttc_common.hpp", "device_common.hpp", "internal.hpp")]
+                  for f in ("ttc_fused.hip", "ttc_common.hpp", "device_common.hpp", "fused.hpp")]
 
 
 def profiled_traffic():

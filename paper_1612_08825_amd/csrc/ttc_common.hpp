@@ -4,7 +4,7 @@
 #pragma once
 
 #include "device_common.hpp"
-#include "internal.hpp"
+#include "fused.hpp"
 
 namespace ttc {
 namespace fused {
