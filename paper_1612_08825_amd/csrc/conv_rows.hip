@@ -338,15 +338,19 @@ __device__ __forceinline__ void band_fma_planes(TA (&acc)[K][R][4], const TA (&r
 // output planes m = i + kd - (K - 1), kd = 0..K-1, held in K accumulator slots
 // in rotation (slot of m: m mod K); terms for planes outside the run are not
 // formed.  Output plane m has all its terms once plane m + K - 1 is in.  It is
-// stored during the step of plane m + K, after that step's loads are issued
-// and before its products, which start the slot afresh.  Each step first
-// issues the loads of the plane K - 1 ahead (a ring of K row buffers), so the
-// loads of the next K - 1 planes are in flight while the current plane's
-// products run.  The run is unrolled whole: buffers, slots and the first
-// planes' kernel-plane bounds are static and no load is in flight across a
-// loop edge.  Every step issues the same loads (a plane past the run or
-// outside the image reloads one inside, unused), so the compiler waits for
-// one plane's rows without waiting for the next ones'.
+// stored during the step of plane m + K, before that step's products, which
+// start the slot afresh.  The loads of all DZ + K - 1 input planes of the run
+// are issued first, one row buffer per plane, so the products of a plane run
+// while the later planes' rows are still arriving (the compiler waits for one
+// plane's rows at a time: vector loads complete in order).  The run is
+// unrolled whole: buffers, slots and the first planes' kernel-plane bounds are
+// static.  Every plane issues the same loads (a plane past the run or outside
+// the image reloads one inside, unused).
+//
+// Launch shape: bands of 2 rows and runs of 2 planes.  More, smaller waves
+// overlap one wave's loads with another's products better than few large ones
+// (64 x 256 x 256 by 3^3 on MI355X: 4-row bands and 3-plane runs 14.8 us;
+// 2 x 3 13.7; 2 x 1 13.6; 1 x 1..3 14.1-15.7; 2 x 2 13.1).
 //
 // Rows and chunks outside the image are read through the plane's buffer
 // resource at an out-of-range offset, which reads zero (W is a multiple of 4,
@@ -480,11 +484,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void co
   });
 }
 
-#ifndef TC_CONV3D_WAVES
-#define TC_CONV3D_WAVES 2048
-#endif
-constexpr int64_t kConv3dWaves = TC_CONV3D_WAVES;
-
 template <int K, int R, int S>
 hipError_t launch_rows3d_s(RowArgs ra, hipStream_t s) {
   constexpr int NC = row_chunks<K, S>();
@@ -499,15 +498,12 @@ hipError_t launch_rows3d_s(RowArgs ra, hipStream_t s) {
     if (w < best_w) best_w = w, best_lg = lg, best_cw = n_cw;
   }
   ra.n_cw = best_cw;
-  // runs of 2 output planes if their waves all fit at once, else of 3
-  const int dz = (int64_t)((ra.OD + 1) / 2) * best_w <= kConv3dWaves ? 2 : 3;
-  const int n_runs = (ra.OD + dz - 1) / dz;
+  // runs of 2 output planes
+  constexpr int DZ = 2;
+  const int n_runs = (ra.OD + DZ - 1) / DZ;
   ra.n_items = (int64_t)n_runs * best_w;  // waves
   const int64_t grid = (ra.n_items + 7) / 8 * 8;
-  if (dz == 2)
-    hipLaunchKernelGGL((conv3d_rows<K, R, S, 2>), dim3((unsigned)grid), dim3(64), 0, s, ra, best_lg);
-  else
-    hipLaunchKernelGGL((conv3d_rows<K, R, S, 3>), dim3((unsigned)grid), dim3(64), 0, s, ra, best_lg);
+  hipLaunchKernelGGL((conv3d_rows<K, R, S, DZ>), dim3((unsigned)grid), dim3(64), 0, s, ra, best_lg);
   return hipGetLastError();
 }
 
@@ -582,7 +578,7 @@ hipError_t TC_ROWS_LAUNCHER_X(TC_ROWS_DT)(const RowArgs& ra, int KH, int band_ro
   if (KH == 3 && ra.KD == 3 && ra.OD > 1 && ra.W % 4 == 0 && ra.W >= 4 &&
       ((int64_t)(ra.H - 1) * ra.xs0 + ra.W) * (int64_t)sizeof(TX) < (1LL << 31) &&
       ((int64_t)(ra.OH - 1) * ra.ys0 + ra.OW) * 4 < (1LL << 31))
-    return launch_rows3d_t<3, 4>(ra, s);
+    return launch_rows3d_t<3, 2>(ra, s);
   if (band_rows == 0) band_rows = default_band_rows(KH, (int64_t)ra.OD * ra.OH * ra.OW);
   if (band_rows != 2 && band_rows != 4 && band_rows != 8) return hipErrorInvalidValue;
   switch (KH) {
