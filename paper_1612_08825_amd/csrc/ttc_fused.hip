@@ -71,12 +71,22 @@ constexpr int kHalo = 1 << (LV - 1);  // rows walked past the band
 constexpr int NV = LV * 10;           // running sums per lane
 
 // Temporal sum and difference of eight pixels of two frames, S = a + b and
-// D = b - a in FP32.  u8: exact conversions and exact sums.  f16: one
-// mixed-precision FMA each (both halves converted exactly, one rounding), with
-// `one` = 1.0 held in a register so that the multiply is not folded away.
+// D = b - a in FP32, each one FMA by `one` = 1.0 held in a register, so that
+// the multiply is not folded away.  u8: exact byte conversions and exact sums
+// (written as plain adds, the compiler turns them into integer adds and then
+// converts every value derived from them, several times the conversions).
+// f16: one mixed-precision FMA each (both halves converted exactly, one
+// rounding).
 __device__ __forceinline__ void sum_diff(const Raw8<uint8_t>& a, const Raw8<uint8_t>& b, float (&S)[8],
-                                         float (&D)[8], float) {
-  b.sum_diff(a, S, D);
+                                         float (&D)[8], float one) {
+  float av[8], bv[8];
+  a.unpack(av);
+  b.unpack(bv);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    S[c] = __builtin_fmaf(bv[c], one, av[c]);
+    D[c] = __builtin_fmaf(bv[c], one, -av[c]);
+  }
 }
 __device__ __forceinline__ void sum_diff(const Raw8<_Float16>& a, const Raw8<_Float16>& b, float (&S)[8],
                                          float (&D)[8], float one) {
