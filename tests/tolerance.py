@@ -9,10 +9,9 @@ Convolution (FP32 accumulation of K products per output, any order):
 TTC sums: the GPU forms FP32 products and sums them per lane in plain FP32
 register blocks of at most BLOCK terms (16 rows x 8 columns at level 0), adds
 the block totals of a band in FP32 (at most BLOCKS of them: 256 / 16 + 1 for
-the tallest band the tuning allows), reduces the 64 lanes of a wave in
-REDUCE_DEPTH rounded additions (three DPP steps within groups of 8 lanes, then
-the 8 group totals added in sequence), and combines the bands with TwoSum in
-the finishing pass.  The error of every sum is therefore bounded by
+the tallest band the tuning allows), adds the owning lanes of a segment (at
+most 63) in a pairwise tree of REDUCE_DEPTH rounded additions, and combines
+the segments with TwoSum in the finishing pass.  The error of every sum is therefore bounded by
     |s - s64| <= TAU_SUM * sum|terms|,
 TAU_SUM = (BLOCK + BLOCKS + REDUCE_DEPTH + 8) * 2^-24; the 8 covers the
 rounding of the products and of G.  The bound on A, B, C follows from first-order perturbation
@@ -37,7 +36,7 @@ import oracle as O
 TAU_CONV = 1e-5
 BLOCK = 16 * 8
 BLOCKS = 256 // 16 + 1
-REDUCE_DEPTH = 3 + 7
+REDUCE_DEPTH = 6  # pairwise tree over 64 slots
 TAU_SUM = (BLOCK + BLOCKS + REDUCE_DEPTH + 8) * 2.0 ** -24
 
 
