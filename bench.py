@@ -222,7 +222,9 @@ def conv_sweep(api, torch, steps, use_graph=True):
     FP32; buffers rotated over >= 1 GiB so that
     the 256 MiB last-level cache cannot serve them.  Timed as a replayed graph of
     the launches (per-launch kernel time); the eager per-call time, which
-    includes the host's call overhead, is reported beside it."""
+    includes the host's call overhead, is reported beside it.  For FP32 cases a
+    plain device copy of the same bytes, timed the same way, is reported too
+    (`copy_same_bytes_ms`, and `speed_vs_copy` = copy time / kernel time)."""
     import numpy as np
 
     from paper_1612_08825_amd import synth
@@ -315,6 +317,27 @@ def conv_sweep(api, torch, steps, use_graph=True):
                      "hbm_frac": round(gbps / HBM_PEAK_GBPS, 3), "alu_frac": round(tf / ALU_PEAK_TFLOPS, 3),
                      "alu_frac_no_packed_fp32": round(tf / ALU_PEAK_NOPACK_TFLOPS, 3),
                      "frac": round(gbps / HBM_PEAK_GBPS if bound == "hbm" else tf / ALU_PEAK_TFLOPS, 3)}
+        if kind == "f32" and not sep:
+            # reference: device-to-device copies of the same buffers that read
+            # the input and write the whole output (the part past the input's
+            # length comes from its head), replayed from a graph the same way
+            n_in, n_out = math.prod(xs), math.prod(ys)
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                for i in range(reps):
+                    xf, yf = xbufs[i % nbuf].view(-1), ybufs[i % nbuf].view(-1)
+                    yf[:n_in].copy_(xf)
+                    yf[n_in:].copy_(xf[:n_out - n_in])
+            graph.replay()
+            torch.cuda.synchronize()
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            copy_ms = e0.elapsed_time(e1) / reps
+            del graph
+            out[name]["copy_same_bytes_ms"] = round(copy_ms, 5)
+            out[name]["speed_vs_copy"] = round(copy_ms / ms, 3)
         del xbufs, ybufs
         torch.cuda.empty_cache()
     return out
