@@ -35,8 +35,8 @@ struct SeqDesc {
   int32_t seg_cols;       // owned base columns per segment (a multiple of 8, at most 504)
   int32_t seg_lanes;      // lanes per segment: seg_cols / 8 + 1
   int32_t seg_per_wave;   // segments per wave: floor(64 / seg_lanes)
-  int32_t n_waves;        // work items per pair: ceil(n_witems / seg_per_wave)
-  int32_t n_witems;       // segments (column strips x bands): partial sums per (pair, level)
+  int32_t n_waves;        // work items per pair: ceil(n_segs / seg_per_wave)
+  int32_t n_segs;         // segments (column strips x bands): partial sums per (pair, level)
   int32_t n_strips;       // column strips: ceil((W - 1) / seg_cols)
   int32_t n_full_bands;   // leading bands whose walk has a row of the frame below it
   int32_t vec;            // 1: every 8-pixel lane chunk is aligned for one vector load

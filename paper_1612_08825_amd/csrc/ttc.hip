@@ -74,8 +74,8 @@ __global__ __launch_bounds__(256) void ttc_finish(FusedArgs a, tc_ttc_level* __r
 #pragma unroll
     for (int q = 0; q < 10; ++q) hi[q] = lo[q] = 0.f;
     const gptr<const float> base =
-        as_global(a.partials + d.partial_begin + (p * LV + l) * (int64_t)d.n_witems * 10);
-    for (int w = lane; w < d.n_witems; w += 64) {
+        as_global(a.partials + d.partial_begin + (p * LV + l) * (int64_t)d.n_segs * 10);
+    for (int w = lane; w < d.n_segs; w += 64) {
 #pragma unroll
       for (int q = 0; q < 10; ++q) comp_add(hi[q], lo[q], base[(int64_t)w * 10 + q]);
     }

@@ -45,7 +45,7 @@ __device__ __forceinline__ SeqDesc uniform(const SeqDesc& s) {
   d.seg_lanes = uni(s.seg_lanes);
   d.seg_per_wave = uni(s.seg_per_wave);
   d.n_waves = uni(s.n_waves);
-  d.n_witems = uni(s.n_witems);
+  d.n_segs = uni(s.n_segs);
   d.n_strips = uni(s.n_strips);
   d.n_full_bands = uni(s.n_full_bands);
   d.vec = uni(s.vec);

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tt
     const int k = lane / SL;
     const int li = lane - k * SL;
     const int sid = wv * SPW + k;
-    const bool seg_ok = k < SPW && sid < d.n_witems;
+    const bool seg_ok = k < SPW && sid < d.n_segs;
     const int sidc = seg_ok ? sid : wv * SPW;  // lanes past the segments walk the first one's rows
     // the full bands strip-major, then the bottom bands band-major
     const int n_full = d.n_strips * d.n_full_bands;
@@ -561,9 +561,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void tt
       else if (SL <= 32) sum = segment_sum<32>(tot, i, ks * SL, SL - 1);
       else sum = segment_sum<64>(tot, i, ks * SL, SL - 1);
       const int s2 = wv * SPW + ks;
-      if (s2 < d.n_witems) {
+      if (s2 < d.n_segs) {
         const int l = i / 10, q = i - (i / 10) * 10;
-        as_global(part)[((int64_t)(pair * LV + l) * d.n_witems + s2) * 10 + q] = sum;
+        as_global(part)[((int64_t)(pair * LV + l) * d.n_segs + s2) * 10 + q] = sum;
       }
     }
     __syncthreads();  // the slots are read before the next item clears them

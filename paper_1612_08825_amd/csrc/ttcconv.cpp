@@ -744,7 +744,7 @@ void choose_segments(SeqDesc& d) {
       d.seg_cols = g.cols;
       d.seg_lanes = g.lanes;
       d.seg_per_wave = g.per_wave;
-      d.n_witems = (int32_t)segs;
+      d.n_segs = (int32_t)segs;
       d.n_waves = (int32_t)waves;
       d.n_strips = (int32_t)strips;
     }
@@ -794,7 +794,7 @@ static int plan_fill(tc_ttc_plan* p, const tc_seq* seqs, int32_t n_seqs) {
     d.partial_begin = floats;
     items += (int64_t)d.n_waves * (d.n_frames - 1);  // one work item per (wave of segments, pair)
     pairs += d.n_frames - 1;
-    floats += (int64_t)(d.n_frames - 1) * p->levels * d.n_witems * 10;
+    floats += (int64_t)(d.n_frames - 1) * p->levels * d.n_segs * 10;
   }
   if (items > INT32_MAX || pairs > INT32_MAX) return TC_EINVAL;
   const size_t desc_bytes = align_up(sizeof(SeqDesc) * (size_t)n_seqs);
@@ -980,7 +980,7 @@ int pair_desc(const tc_tensor* prev, const tc_tensor* next, int32_t levels, SeqD
   return TC_OK;
 }
 
-size_t pair_ws_bytes(const SeqDesc& d) { return align_up((size_t)d.levels * d.n_witems * 10 * sizeof(float)); }
+size_t pair_ws_bytes(const SeqDesc& d) { return align_up((size_t)d.levels * d.n_segs * 10 * sizeof(float)); }
 
 }  // namespace
 
