@@ -160,7 +160,14 @@ def test_batched_workload_sampled(api):
     assert picks.shape == (64 * 15,)
     big = max(range(64), key=lambda i: specs[i].H * specs[i].W)
     small = min(range(64), key=lambda i: specs[i].H * specs[i].W)
-    for s_i, t in ((big, 7), (small, 0), (5, 14)):
+    # one stream of every size: each size gets its own column-strip shape
+    # (1920 and 320 wide one 504-column strip per wave, 640 two of 248, 1280 three of 160)
+    first = {}
+    for i, s in enumerate(specs):
+        first.setdefault((s.W, s.H), i)
+    assert len(first) == 4
+    samples = [(big, 7), (small, 0), (5, 14)] + [(i, 3) for i in first.values() if i not in (big, small)]
+    for s_i, t in samples:
         host = vids[s_i].cpu().numpy()
         g = s_i * 15 + t
         check_pair(recs[g * 4:(g + 1) * 4], picks[g], host[t], host[t + 1], 4, f"stream{s_i}")
