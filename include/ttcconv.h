@@ -357,9 +357,11 @@ typedef struct tc_ttc_plan tc_ttc_plan;
  * pair_base(s) = sum over earlier streams of (n_frames - 1). */
 int tc_ttc_plan_create(const tc_seq* seqs, int32_t n_seqs, int32_t dtype, tc_ttc_plan** plan);
 
-/* Launch shape of the fused pass.  band_rows: base rows one wave walks for
- * one frame pair (a multiple of 16 from 16 to 256; taller bands walk fewer
- * halo rows per owned row and give fewer, longer work items); groups_per_cu:
+/* Launch shape of the fused pass.  band_rows: base rows of each band a wave
+ * walks for one frame pair (a multiple of 16 from 16 to 256; a wave holds one
+ * to four bands of column strips side by side, the strip width chosen per
+ * stream; taller bands walk fewer halo rows per owned row and give fewer,
+ * longer work items); groups_per_cu:
  * work-groups (one wave each) of the persistent grid per compute unit
  * (1..256).  The sums depend on band_rows through their blocking (not on
  * groups_per_cu); a fixed tuning gives bit-identical results for a stream
