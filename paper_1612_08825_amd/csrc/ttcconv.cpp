@@ -683,11 +683,12 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // count: the best of the fused pass's tuning sweep (autotune.py) on MI355X,
 // f16 on the 64-stream batched workload, u8 on a 64-stream serving mix.  More
 // work-groups than items means one item per work-group, dispatched by the
-// hardware.  With column strips packed per wave, 160-row bands measured within
-// 1.3% of 128 (noise between runs is about 2%), so 128 stays.
+// hardware.  With column strips packed per wave every case is best at 128 rows
+// x 128 work-groups per CU (the runner-up within 0.1-4%); 160-row bands, outside
+// the sweep, measured within 1% of 128 on f16 at 4 levels.
 tc_ttc_tuning default_tuning(int dtype, int levels) {
-  static const tc_ttc_tuning f16[TC_MAX_LEVELS] = {{128, 128}, {128, 64}, {128, 128}, {128, 128}};
-  static const tc_ttc_tuning u8[TC_MAX_LEVELS] = {{64, 128}, {64, 128}, {64, 128}, {128, 64}};
+  static const tc_ttc_tuning f16[TC_MAX_LEVELS] = {{128, 128}, {128, 128}, {128, 128}, {128, 128}};
+  static const tc_ttc_tuning u8[TC_MAX_LEVELS] = {{128, 128}, {128, 128}, {128, 128}, {128, 128}};
   const int l = levels < 1 ? 0 : (levels > TC_MAX_LEVELS ? TC_MAX_LEVELS - 1 : levels - 1);
   return dtype == TC_U8 ? u8[l] : f16[l];
 }

@@ -249,8 +249,8 @@ def test_ttc_plan_validation(lib):
 def test_ttc_tuning_defaults_and_rejections(lib):
     t = L.TcTuning()
     # the sweep's choices, per frame type and level count
-    want = {(L.TC_F16, 4): (128, 128), (L.TC_F16, 2): (128, 64), (L.TC_F16, 1): (128, 128), (L.TC_U8, 3): (64, 128),
-            (L.TC_U8, 4): (128, 64)}
+    want = {(L.TC_F16, 4): (128, 128), (L.TC_F16, 2): (128, 128), (L.TC_F16, 1): (128, 128), (L.TC_U8, 3): (128, 128),
+            (L.TC_U8, 4): (128, 128)}
     for (dt, lv), shape in want.items():
         assert lib.tc_ttc_tuning_default(dt, lv, C.byref(t)) == 0
         assert (t.band_rows, t.groups_per_cu) == shape, (dt, lv)
