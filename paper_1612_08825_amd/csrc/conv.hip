@@ -692,11 +692,11 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
     return launch_rows(ra, (int)c.kshape[r - 2], c.xdt, c.band_rows, s);
   }
 
-  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernel rows up to 48
-  // taps with up to 64 rows, or up to 64 taps with up to 48 rows, which keeps
-  // the staged tile within 64 KiB of LDS (at most 127 x 112 or 111 x 128 elements).
+  // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernels of up to 64 x 64
+  // taps; the staged tile stays within 64 KiB of LDS (at most 127 rows by a
+  // pitch of 128 elements: 65,024 bytes).
   const int64_t kh = c.kshape[r - 2], kw = c.kshape[r - 1];
-  const bool tiled_ok = (r == 2 || r == 3) && small_taps && ((kw <= 48 && kh <= 64) || (kw <= 64 && kh <= 48)) &&
+  const bool tiled_ok = (r == 2 || r == 3) && small_taps && kw <= 64 && kh <= 64 &&
                         c.xshape[r - 1] < (1LL << 30) && c.xshape[r - 2] < (1LL << 30) &&
                         c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&
                         c.off[r - 1] < (1LL << 30) && c.off[r - 2] < (1LL << 30) &&

@@ -44,9 +44,9 @@ SHAPES_2D = [((70, 130), (3, 3)), ((129, 65), (7, 7)), ((100, 77), (15, 15)), ((
              ((70, 560), (15, 15)), ((9, 300), (15, 15)),
              # the 32-wide tiled kernel (kernel rows of 17..32 taps)
              ((150, 140), (23, 23)), ((80, 200), (17, 31)), ((70, 66), (64, 32)), ((20, 25), (31, 31)),
-             # the 48- and 64-wide tiled kernels (rows of 33..48 taps with up to 64 rows,
-             # 49..64 taps with at most 48 rows)
-             ((90, 150), (47, 47)), ((40, 300), (48, 64)), ((66, 70), (33, 40)), ((100, 90), (64, 48))]
+             # the 48- and 64-wide tiled kernels (rows of 33..64 taps, up to 64 rows)
+             ((90, 150), (47, 47)), ((40, 300), (48, 64)), ((66, 70), (33, 40)), ((100, 90), (64, 48)),
+             ((100, 90), (64, 64)), ((70, 80), (63, 57))]
 
 
 @pytest.mark.parametrize("xs,ks", SHAPES_2D)
