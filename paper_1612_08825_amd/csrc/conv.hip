@@ -16,6 +16,7 @@
 // The generic kernel visits taps in kernel-row-major order for every output
 // element, the tiled kernel kernel rows first to last and the taps within a
 // row last to first; conv2d_rows visits tap rows from last to first.
+#include <algorithm>
 #include <type_traits>
 
 #include "conv_common.hpp"
@@ -31,6 +32,7 @@ constexpr int kTX = 16, kTY = 16;   // threads per work-group (x, y)
 constexpr int kRX = 4, kRY = 4;     // outputs per thread (x, y)
 constexpr int kTileX = kTX * kRX;   // 64 output columns per work-group
 constexpr int kTileY = kTY * kRY;   // 64 output rows per work-group
+constexpr int kKernelBlock = 64;     // largest kernel extent one tiled launch takes
 
 template <typename TX> struct Acc { using type = float; };
 template <> struct Acc<uint8_t> { using type = int; };
@@ -49,7 +51,7 @@ template <typename TX> __device__ __forceinline__ typename Acc<TX>::type load_x(
 }
 template <> __device__ __forceinline__ float load_x<_Float16>(const _Float16* x, int64_t i) { return (float)x[i]; }
 
-template <typename TA> __device__ __forceinline__ TA load_k(const void* k, int i) {
+template <typename TA> __device__ __forceinline__ TA load_k(const void* k, int64_t i) {
   return reinterpret_cast<const TA*>(k)[i];
 }
 
@@ -66,6 +68,11 @@ struct Tile2D {
   // 3-D extension (plane dimension); D == 1 and KD == 1 for plain 2-D.
   int64_t xsd, ysd;
   int D, KD, OD, offd;
+  // the taps: k[kd * ksd + ky * ks0 + kx] (a block of a larger kernel when
+  // ks0 > KW); accumulate: add into y instead of writing it
+  int ks0;
+  int64_t ksd;
+  int accumulate;
 };
 
 // Stage the input tile whose top-left corner is (r0, c0) of plane `xp`.
@@ -88,8 +95,8 @@ __device__ __forceinline__ void stage_tile(typename Acc<TX>::type* lds, const TX
 
 // acc += sum over taps of kernel plane `kp` of the staged tile.
 template <typename TA, int KWMAX, int PITCH>
-__device__ __forceinline__ void tile_fma(TA (&acc)[kRY][kRX], const TA* lds, const void* k, int kp_off, int KH,
-                                         int KW) {
+__device__ __forceinline__ void tile_fma(TA (&acc)[kRY][kRX], const TA* lds, const void* k, int64_t kp_off, int KH,
+                                         int KW, int ks0) {
   const int tx = threadIdx.x, ty = threadIdx.y;
   for (int ky = 0; ky < KH; ++ky) {
     // the taps of kernel row ky from last to first, kt[j] = k[ky][KW - 1 - j],
@@ -97,7 +104,7 @@ __device__ __forceinline__ void tile_fma(TA (&acc)[kRY][kRX], const TA* lds, con
     // static register index for every j)
     TA kt[KWMAX];
 #pragma unroll
-    for (int j = 0; j < KWMAX; ++j) kt[j] = (j < KW) ? load_k<TA>(k, kp_off + ky * KW + (KW - 1 - j)) : (TA)0;
+    for (int j = 0; j < KWMAX; ++j) kt[j] = (j < KW) ? load_k<TA>(k, kp_off + (int64_t)ky * ks0 + (KW - 1 - j)) : (TA)0;
 #pragma unroll
     for (int ry = 0; ry < kRY; ++ry) {
       const TA* row = lds + (ty * kRY + ry + (KH - 1 - ky)) * PITCH + tx * kRX;
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(256) void conv2d_tiled(Tile2D a) {
       __syncthreads();
       stage_tile<TX, PITCH>(lds, x + (int64_t)xd * a.xsd, a, r0, c0, rows, cols);
       __syncthreads();
-      tile_fma<TA, KWMAX, PITCH>(acc, lds, a.k, kd * a.KH * a.KW, a.KH, a.KW);
+      tile_fma<TA, KWMAX, PITCH>(acc, lds, a.k, kd * a.ksd, a.KH, a.KW, a.ks0);
     }
 
     TA* y = reinterpret_cast<TA*>(a.y) + (int64_t)od * a.ysd;
@@ -158,7 +165,10 @@ __global__ __launch_bounds__(256) void conv2d_tiled(Tile2D a) {
 #pragma unroll
       for (int rx = 0; rx < kRX; ++rx) {
         const int p = p0 + threadIdx.x * kRX + rx;
-        if (p < a.OW) y[(int64_t)o * a.ys0 + (int64_t)p * a.ys1] = acc[ry][rx];
+        if (p < a.OW) {
+          TA& out = y[(int64_t)o * a.ys0 + (int64_t)p * a.ys1];
+          out = a.accumulate ? out + acc[ry][rx] : acc[ry][rx];
+        }
       }
     }
   }
@@ -694,9 +704,13 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
 
   // Other 2-D and 3-D cases: the LDS-tiled kernels, for kernels of up to 64 x 64
   // taps; the staged tile stays within 64 KiB of LDS (at most 127 rows by a
-  // pitch of 128 elements: 65,024 bytes).
+  // pitch of 128 elements: 65,024 bytes).  A kernel of up to 256 x 256 taps is
+  // split into blocks of at most 64 x 64: block (bi, bj), taps from
+  // (64 bi, 64 bj), contributes conv(x, block) at full index n - (64 bi, 64 bj),
+  // so each block runs with its output offset moved back by its origin, the
+  // first writing the output and the others adding to it, in a fixed order.
   const int64_t kh = c.kshape[r - 2], kw = c.kshape[r - 1];
-  const bool tiled_ok = (r == 2 || r == 3) && small_taps && kw <= 64 && kh <= 64 &&
+  const bool tiled_ok = (r == 2 || r == 3) && small_taps && kw <= 4 * kKernelBlock && kh <= 4 * kKernelBlock &&
                         c.xshape[r - 1] < (1LL << 30) && c.xshape[r - 2] < (1LL << 30) &&
                         c.yshape[r - 1] < (1LL << 30) && c.yshape[r - 2] < (1LL << 30) &&
                         c.off[r - 1] < (1LL << 30) && c.off[r - 2] < (1LL << 30) &&
@@ -733,11 +747,27 @@ hipError_t launch_conv(const ConvND& c, bool small_taps, hipStream_t s) {
       t.OD = 1;
       t.offd = 0;
     }
-    const int kwmax = t.KW <= 4 ? 4 : t.KW <= 8 ? 8 : t.KW <= 16 ? 16 : t.KW <= 32 ? 32 : t.KW <= 48 ? 48 : 64;
+    t.ks0 = (int)kw;
+    t.ksd = kh * kw;
     const int64_t n_ty = (t.OH + kTileY - 1) / kTileY;
     const dim3 grid((unsigned)((t.OW + kTileX - 1) / kTileX), (unsigned)(n_ty < 65535 ? n_ty : 65535),
                     (unsigned)t.OD);
-    return launch_tiled(c.xdt, t, kwmax, grid, s);
+    const int off0 = t.off0, off1 = t.off1;
+    for (int bi = 0; bi * kKernelBlock < kh; ++bi) {
+      for (int bj = 0; bj * kKernelBlock < kw; ++bj) {
+        Tile2D b = t;
+        b.KH = (int)std::min<int64_t>(kKernelBlock, kh - bi * kKernelBlock);
+        b.KW = (int)std::min<int64_t>(kKernelBlock, kw - bj * kKernelBlock);
+        b.k = static_cast<const char*>(c.k) + ((int64_t)bi * kKernelBlock * kw + (int64_t)bj * kKernelBlock) * 4;
+        b.off0 = off0 - bi * kKernelBlock;
+        b.off1 = off1 - bj * kKernelBlock;
+        b.accumulate = (bi | bj) != 0;
+        const int kwmax = b.KW <= 4 ? 4 : b.KW <= 8 ? 8 : b.KW <= 16 ? 16 : b.KW <= 32 ? 32 : b.KW <= 48 ? 48 : 64;
+        const hipError_t e = launch_tiled(c.xdt, b, kwmax, grid, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
   }
 
   GenericArgs g{};

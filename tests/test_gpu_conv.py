@@ -76,6 +76,28 @@ def test_conv2d_u8_exact(api, xs, ks, mode):
     np.testing.assert_array_equal(y.astype(np.int64), O.conv(x, k, mode))
 
 
+@pytest.mark.parametrize("xs,ks", [((130, 140), (95, 80)), ((40, 50), (65, 70)), ((70, 300), (20, 129)),
+                                   ((4, 80, 90), (2, 66, 70)), ((10, 12), (3, 260))])
+@pytest.mark.parametrize("mode", ["full", "same", "valid"])
+def test_conv_kernel_blocks(api, xs, ks, mode):
+    """Kernels over 64 taps along a row or column run as 64 x 64 blocks of the
+    tiled kernel, the first writing the output and the rest adding to it (a
+    kernel over 256 taps takes the generic kernel): FP32 within the bound, u8 *
+    i32 bit for bit."""
+    try:
+        O.conv_out_shape(xs, ks, mode)
+    except ValueError:
+        pytest.skip("mixed extents are rejected in valid mode")
+    x = synth.conv_image(xs, case=6)
+    k = synth.conv_kernel(ks, case=6)
+    y = api.conv_nd(torch.from_numpy(x).cuda(), torch.from_numpy(k).cuda(), mode).cpu().numpy()
+    _check_float(y, x, k, mode, f"blocks {xs}*{ks} {mode}")
+    xu = synth.conv_image(xs, case=6, dtype="u8")
+    ku = synth.conv_kernel(ks, case=6, dtype="i32")
+    yu = api.conv_nd(torch.from_numpy(xu).cuda(), torch.from_numpy(ku).cuda(), mode).cpu().numpy()
+    np.testing.assert_array_equal(yu.astype(np.int64), O.conv(xu, ku, mode))
+
+
 def test_conv2d_f16_input(api):
     x = synth.conv_image((90, 75), case=3, dtype="f16")
     k = synth.conv_kernel((5, 5), case=3)
