@@ -16,8 +16,10 @@
  *    launch is asynchronous on that stream; no entry point synchronises except
  *    tc_ttc_solve_batched and tc_ttc_plan_destroy, which say so.
  *  - No entry point allocates or frees device memory.
- *  - A negative return value means the arguments were rejected and nothing
- *    was launched.  No C++ exception crosses this interface.
+ *  - A negative return value other than TC_EDEVICE means the arguments were
+ *    rejected and nothing was launched.  TC_EDEVICE reports a launch the
+ *    runtime refused; in calls made of several launches, the ones before it
+ *    may have run.  No C++ exception crosses this interface.
  *  - Strides are in elements and row-major (the last dimension is the
  *    fastest).  A stride of 0 on a dimension of extent > 1 is rejected.
  */
